@@ -1,0 +1,326 @@
+"""Seeded synthetic inputs for LDPC syndrome decoding (QKD reconciliation).
+
+This module is shared by the CPU oracle's tests and by the HIP path's tests and
+benchmark. It holds none of the decoder's arithmetic. It only produces what a
+decoder receives:
+
+* a quasi-cyclic (QC) base matrix: an Mb x Nb array of circulant shifts, -1 for
+  an all-zero block (Sec. 4.1 of the paper describes QC codes built from a base
+  matrix and a lift Z; its own 100 kb irregular codes are not public, so seeded
+  random regular bases of girth >= 6 stand in for them);
+* Alice's key x, the binary-symmetric-channel errors e and Bob's key y = x ^ e;
+* Alice's syndrome s = Hx, bit-packed LSB-first (bit i -> byte i >> 3, bit i & 7);
+* Bob's channel LLRs quantized to int8, positive meaning bit 0;
+* the positions that rate adaptation punctures or shortens (Sec. 4.1: low
+  column weight first; shortened bits are taken in turn from the puncture list).
+
+Circulant convention: block (b, c) with shift s connects row b*Z + r to column
+c*Z + (r + s) mod Z.
+
+All randomness comes from numpy's Philox counter-based generator keyed by
+(seed, stream, frame), so frame f of a batch is the same whatever the batch
+size.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Quantization step of the integer message domain. The paper does not print it;
+# fitting Alg. 1 to the exact box-plus table it stands for (Sec. 3.2) puts it in
+# [0.3031, 0.3135]; 5/16 is the binary fraction in that range.
+DELTA = 5.0 / 16.0
+LLR_MAX = 127
+
+_STREAM_CODE = 1
+_STREAM_ORDER = 2
+_STREAM_FRAME = 3
+
+
+def _rng(seed: int, stream: int, index: int = 0) -> np.random.Generator:
+    key = ((int(seed) & 0xFFFFFFFF) << 64) | ((stream & 0xFFFF) << 48) | (int(index) & ((1 << 48) - 1))
+    return np.random.Generator(np.random.Philox(key=key))
+
+
+# ---------------------------------------------------------------------------
+# Code construction
+# ---------------------------------------------------------------------------
+
+def _pair_diffs_ok(base: np.ndarray, z: int, col: int) -> bool:
+    """True when column `col` closes no length-4 cycle with columns < col.
+
+    A 4-cycle through rows r1, r2 and columns c1, c2 exists iff
+    s[r1,c1] - s[r2,c1] == s[r1,c2] - s[r2,c2] (mod Z).
+    """
+    rows = np.nonzero(base[:, col] >= 0)[0]
+    for i in range(len(rows)):
+        for k in range(i + 1, len(rows)):
+            r1, r2 = rows[i], rows[k]
+            d_new = (base[r1, col] - base[r2, col]) % z
+            prev = np.nonzero((base[r1, :col] >= 0) & (base[r2, :col] >= 0))[0]
+            if len(prev) and np.any((base[r1, prev] - base[r2, prev]) % z == d_new):
+                return False
+    return True
+
+
+def make_base(mb: int, nb: int, z: int, col_weight: int = 3, seed: int = 1903,
+              max_tries: int = 2000) -> np.ndarray:
+    """Random regular QC base matrix: every column has `col_weight` nonzero
+    blocks, row weights differ by at most one, shifts are uniform on [0, Z), and
+    no 4-cycle is closed when Z permits (each column is resampled until it
+    closes none, up to `max_tries` times; after that the column is kept)."""
+    if not (1 <= col_weight <= mb):
+        raise ValueError("col_weight must be in [1, mb]")
+    rng = _rng(seed, _STREAM_CODE, (mb << 32) | (nb << 16) | (z & 0xFFFF))
+    base = -np.ones((mb, nb), dtype=np.int32)
+    row_w = np.zeros(mb, dtype=np.int64)
+    for c in range(nb):
+        # the col_weight least-loaded rows, ties broken at random
+        keys = row_w * 4096 + rng.permutation(mb)
+        rows = np.sort(np.argsort(keys, kind="stable")[:col_weight])
+        row_w[rows] += 1
+        for _ in range(max_tries):
+            base[:, c] = -1
+            base[rows, c] = rng.integers(0, z, size=col_weight)
+            if _pair_diffs_ok(base, z, c):
+                break
+    return base
+
+
+def array_code_base(q: int, rows: int, cols: int) -> np.ndarray:
+    """Array-code base matrix with shifts (i * j) mod q (girth 6 for prime q)."""
+    return np.array([[(i * j) % q for j in range(cols)] for i in range(rows)], dtype=np.int32)
+
+
+def has_4cycle(base: np.ndarray, z: int) -> bool:
+    for c in range(base.shape[1]):
+        if not _pair_diffs_ok(base, z, c):
+            return True
+    return False
+
+
+@dataclass
+class Code:
+    base: np.ndarray  # int32 [mb, nb], -1 = zero block
+    z: int
+
+    @property
+    def mb(self) -> int:
+        return int(self.base.shape[0])
+
+    @property
+    def nb(self) -> int:
+        return int(self.base.shape[1])
+
+    @property
+    def n(self) -> int:
+        return self.nb * self.z
+
+    @property
+    def m(self) -> int:
+        return self.mb * self.z
+
+    @property
+    def n_blocks(self) -> int:
+        return int((self.base >= 0).sum())
+
+    @property
+    def n_edges(self) -> int:
+        return self.n_blocks * self.z
+
+    @property
+    def rate(self) -> float:
+        return 1.0 - self.m / self.n
+
+    def column_weights(self) -> np.ndarray:
+        """Weight of every column of the lifted H, length n."""
+        return np.repeat((self.base >= 0).sum(axis=0), self.z)
+
+
+# ---------------------------------------------------------------------------
+# Frames
+# ---------------------------------------------------------------------------
+
+def syndrome_bits(code: Code, x: np.ndarray) -> np.ndarray:
+    """Alice's syndrome s = Hx over GF(2) as a 0/1 array [F, m] (the step
+    before the decoder; kept here so that inputs never come from the decoder)."""
+    x = np.atleast_2d(x).astype(np.uint8)
+    f = x.shape[0]
+    z = code.z
+    s = np.zeros((f, code.m), dtype=np.uint8)
+    for b in range(code.mb):
+        acc = np.zeros((f, z), dtype=np.uint8)
+        for c in range(code.nb):
+            sh = int(code.base[b, c])
+            if sh < 0:
+                continue
+            blk = x[:, c * z:(c + 1) * z]
+            acc ^= np.roll(blk, -sh, axis=1)  # acc[r] ^= x[c*Z + (r + sh) % Z]
+        s[:, b * z:(b + 1) * z] = acc
+    return s
+
+
+def pack_bits(bits: np.ndarray) -> np.ndarray:
+    """0/1 array [..., L] -> uint8 [..., ceil(L/8)], LSB-first."""
+    return np.packbits(np.asarray(bits, dtype=np.uint8), axis=-1, bitorder="little")
+
+
+def unpack_bits(packed: np.ndarray, length: int) -> np.ndarray:
+    return np.unpackbits(np.asarray(packed, dtype=np.uint8), axis=-1, bitorder="little")[..., :length]
+
+
+def channel_llr(qber: float) -> float:
+    """ln((1 - q) / q): the magnitude of a BSC channel LLR."""
+    return math.log((1.0 - qber) / qber)
+
+
+def quantize_llr_mag(qber: float, delta: float = DELTA) -> int:
+    """Integer magnitude of a channel LLR: floor(|ln((1-q)/q)| / delta) capped at 127
+    (bin index of a mid-rise quantizer with step delta)."""
+    return int(min(math.floor(abs(channel_llr(qber)) / delta), LLR_MAX))
+
+
+def position_order(code: Code, seed: int = 1903) -> np.ndarray:
+    """Candidate order for rate adaptation: ascending column weight, ties broken
+    by a seeded permutation. Punctured positions are the first p of this order,
+    shortened positions the next s."""
+    rng = _rng(seed, _STREAM_ORDER, code.n)
+    perm = rng.permutation(code.n)
+    w = code.column_weights()
+    return perm[np.argsort(w[perm], kind="stable")].astype(np.int64)
+
+
+def binary_entropy(q: float) -> float:
+    if q <= 0.0 or q >= 1.0:
+        return 0.0
+    return -q * math.log2(q) - (1 - q) * math.log2(1 - q)
+
+
+@dataclass
+class Frames:
+    code: Code
+    x: np.ndarray            # uint8 [F, n] Alice's bits
+    y: np.ndarray            # uint8 [F, n] Bob's bits
+    syn: np.ndarray          # uint8 [F, ceil(m/8)] packed Hx
+    llr: np.ndarray          # int8 [F, n]
+    llr_f: np.ndarray        # float64 [F, n] exact channel LLRs (0 punctured, +-inf shortened -> large)
+    qber: np.ndarray         # float64 [F]
+    n_punct: np.ndarray      # int64 [F]
+    n_short: np.ndarray      # int64 [F]
+    key_mask: np.ndarray = field(default=None)  # bool [F, n]: positions carrying key
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.x.shape[0])
+
+    def key_bits(self) -> np.ndarray:
+        """Key bits carried by each frame: n - p - s."""
+        return self.code.n - self.n_punct - self.n_short
+
+
+SHORTENED_LLR_F = 1.0e3  # stands for an infinite LLR in the float domain
+
+
+def make_frames(code: Code, n_frames: int, qber, seed: int, *, n_short=0, n_punct=0,
+                frame_offset: int = 0, fixed_weight: bool = False,
+                order: np.ndarray | None = None) -> Frames:
+    """Synthetic BSC frames.
+
+    qber, n_short and n_punct are scalars or per-frame arrays. Frame f draws all
+    of its randomness from Philox keyed by (seed, frame_offset + f).
+
+    * x ~ Bernoulli(1/2); e ~ Bernoulli(q) i.i.d. (or exactly round(q * n_key)
+      errors when fixed_weight); y = x ^ e.
+    * Punctured positions: Bob knows nothing (LLR 0) and x there carries no key.
+    * Shortened positions: the value is revealed, so Bob's LLR is +-127 with the
+      sign of x there.
+    * LLRs elsewhere: +-floor(ln((1-q)/q) / DELTA), positive for y = 0.
+    """
+    n = code.n
+    qv = np.broadcast_to(np.asarray(qber, dtype=np.float64), (n_frames,)).copy()
+    sv = np.broadcast_to(np.asarray(n_short, dtype=np.int64), (n_frames,)).copy()
+    pv = np.broadcast_to(np.asarray(n_punct, dtype=np.int64), (n_frames,)).copy()
+    if np.any(sv + pv > n) or np.any(sv < 0) or np.any(pv < 0):
+        raise ValueError("n_short + n_punct must lie in [0, n]")
+    if order is None and (np.any(sv) or np.any(pv)):
+        order = position_order(code)
+    x = np.empty((n_frames, n), dtype=np.uint8)
+    y = np.empty((n_frames, n), dtype=np.uint8)
+    llr = np.empty((n_frames, n), dtype=np.int8)
+    llr_f = np.empty((n_frames, n), dtype=np.float64)
+    key_mask = np.ones((n_frames, n), dtype=bool)
+    for f in range(n_frames):
+        rng = _rng(seed, _STREAM_FRAME, frame_offset + f)
+        xf = rng.integers(0, 2, size=n, dtype=np.uint8)
+        q = float(qv[f])
+        if fixed_weight:
+            w = int(round(q * n))
+            e = np.zeros(n, dtype=np.uint8)
+            e[rng.choice(n, size=w, replace=False)] = 1
+        else:
+            e = (rng.random(n) < q).astype(np.uint8)
+        yf = xf ^ e
+        mag = quantize_llr_mag(q)
+        lf = np.where(yf == 0, mag, -mag).astype(np.int8)
+        lff = np.where(yf == 0, 1.0, -1.0) * channel_llr(q)
+        p, s = int(pv[f]), int(sv[f])
+        if p:
+            pos = order[:p]
+            lf[pos] = 0
+            lff[pos] = 0.0
+            key_mask[f, pos] = False
+        if s:
+            pos = order[p:p + s]
+            lf[pos] = np.where(xf[pos] == 0, LLR_MAX, -LLR_MAX).astype(np.int8)
+            lff[pos] = np.where(xf[pos] == 0, SHORTENED_LLR_F, -SHORTENED_LLR_F)
+            yf = yf.copy()
+            yf[pos] = xf[pos]
+            key_mask[f, pos] = False
+        x[f], y[f], llr[f], llr_f[f] = xf, yf, lf, lff
+    syn = pack_bits(syndrome_bits(code, x))
+    return Frames(code=code, x=x, y=y, syn=syn, llr=llr, llr_f=llr_f, qber=qv,
+                  n_punct=pv, n_short=sv, key_mask=key_mask)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (shapes of the method's operating points)
+# ---------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    mb: int
+    nb: int
+    z: int
+    frames: int
+    qber: float
+    max_iter: int
+    acc_bits: int = 8
+    short_frac: float = 0.0
+
+    def code(self, seed: int = 1903) -> Code:
+        return Code(make_base(self.mb, self.nb, self.z, 3, seed), self.z)
+
+    @property
+    def n(self) -> int:
+        return self.nb * self.z
+
+
+WORKLOADS = {
+    # short frames, low QBER: 5x32 base, Z = 32 (n = 1024, R = 27/32)
+    "n1024_q1": Workload("n1024_q1", 5, 32, 32, 64, 0.01, 50),
+    # realistic length, QBER 2%: 5x32 base, Z = 1024 (n = 32768, R = 27/32);
+    # shortened so that the frame error rate is at most 1e-2
+    "n32768_q2": Workload("n32768_q2", 5, 32, 1024, 256, 0.02, 50, 8, 0.25),
+    # literal rate 27/32 at QBER 2% (above the BP threshold: FER near 1)
+    "n32768_q2_literal": Workload("n32768_q2_literal", 5, 32, 1024, 256, 0.02, 50),
+    # learned-offset workload: 5x32 base, Z = 256 (n = 8192)
+    "n8192_q2": Workload("n8192_q2", 5, 32, 256, 512, 0.02, 20),
+    # large frames: 10x64 base, Z = 16384 (n = 1048576), int16 soft values
+    "n1048576_q2": Workload("n1048576_q2", 10, 64, 16384, 32, 0.02, 80, 16),
+    # rate-adaptive mother code: 24x48 base, Z = 2048 (n = 98304, R = 1/2)
+    "n98304_ragged": Workload("n98304_ragged", 24, 48, 2048, 2048, 0.04, 60),
+}
