@@ -1,0 +1,149 @@
+/*
+ * qkdldpc: C ABI of an MI355X (gfx950) decoder for quantized layered
+ * belief-propagation decoding of LDPC syndromes, as used in QKD information
+ * reconciliation (Mao, Li, Han, Guo, "High Throughput and Low Cost LDPC
+ * Reconciliation for Quantum Key Distribution", arXiv:1903.10107).
+ *
+ * Bob holds soft values for his sifted key y and receives Alice's syndrome
+ * s = Hx; the decoder returns x^ with H x^ = s when it converges (Sec. 2 of the
+ * paper: layered schedule, Eqs. 1, 7, 8, 9, stopping rule; Sec. 3: 8-bit
+ * messages, improved-RCBP check node of Alg. 1, saturation-oriented variable
+ * node of Alg. 2).
+ *
+ * Memory: every array argument of the decode calls is a DEVICE pointer (for
+ * instance from a torch tensor on the GPU); the base matrix and the parameter
+ * block of ldpc_code_create are HOST pointers and are copied. The caller owns
+ * every buffer it passes; the library owns the code handle and the device
+ * tables behind it. All decode calls are asynchronous with respect to the host
+ * and ordered on the given stream (a hipStream_t; NULL is the null stream).
+ *
+ * Errors: every int-returning call returns LDPC_OK (0) or a negative code and
+ * then sets a thread-local message readable with ldpc_last_error(). Arguments
+ * are checked on the host before anything reaches the device, so invalid
+ * arguments never launch a kernel. Non-convergence of a frame is not an error.
+ *
+ * Bit packing (syndromes and decoded bits): bit i lives in byte i >> 3 at bit
+ * position i & 7 (LSB first).
+ *
+ * Circulant convention: block (b, c) of the base matrix with shift s joins
+ * check row b*Z + r to variable column c*Z + (r + s) mod Z; -1 is a zero block.
+ */
+#ifndef QKDLDPC_H
+#define QKDLDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldpc_code ldpc_code;
+
+enum {
+    LDPC_OK = 0,
+    LDPC_EINVAL = -1,      /* invalid argument */
+    LDPC_ENOMEM = -2,      /* host or device allocation failed */
+    LDPC_EDEVICE = -3,     /* a HIP call or kernel launch failed, or no GPU */
+    LDPC_EUNSUPPORTED = -4 /* valid, but outside what the kernels implement */
+};
+
+/* Check-node rules. The degree-d box-plus of Eq. 4 evaluated with the integer
+ * tau of Alg. 1 (Sec. 3.2) depends on the fold order because tau is not
+ * associative. */
+enum {
+    LDPC_RULE_RCBP_FB = 0,  /* forward-backward order (default) */
+    LDPC_RULE_RCBP_EQ7 = 1, /* literal right fold of Eq. 7 in ascending edge order */
+    LDPC_RULE_MINSUM = 2    /* min-sum: min1/min2/argmin of the magnitudes (Sec. 2 cites it) */
+};
+
+/* Decoder parameters. A zero-initialised block selects the paper's decoder. */
+typedef struct {
+    int32_t msg_max;        /* MSG_max of Alg. 1: largest CN message magnitude; 0 -> 63; range 1..127 */
+    int32_t e_max;          /* E_max of Alg. 2: saturation of the soft values; 0 -> 127 (8-bit)
+                               or 32767 (16-bit); range 1..127 (8-bit), 1..32767 (16-bit) */
+    int32_t acc_bits;       /* width of the soft values E: 0 or 8 -> int8, 16 -> int16 */
+    int32_t cn_rule;        /* LDPC_RULE_* */
+    const int8_t *offsets;  /* HOST pointer or NULL: [offset_iters][n_blocks] magnitude offsets,
+                               subtracted from every CN message magnitude at iteration t using
+                               row min(t-1, offset_iters-1), result clamped to [0, msg_max];
+                               copied at create. NULL = no offsets (the paper's decoder). */
+    int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
+} ldpc_params;
+
+/* Build a code from a quasi-cyclic base matrix (Sec. 4.1).
+ * base: HOST, int32 [mb][nb] row-major; -1 = zero block, 0..z-1 = circulant shift.
+ * Requirements: 1 <= mb < nb; z >= 1; nb * z < 2^31; every base row has
+ * between 2 and 32 nonzero blocks; every base column has at least one.
+ * Base matrices with 4-cycles are accepted and reported by ldpc_code_dims.
+ * params: HOST or NULL (defaults). On success *out receives the handle; the
+ * device tables live on the device current at this call.
+ * Returns LDPC_EINVAL on a bad argument, LDPC_EUNSUPPORTED for a row degree
+ * above 32, LDPC_ENOMEM / LDPC_EDEVICE when the device tables cannot be made. */
+int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z,
+                     const ldpc_params *params, ldpc_code **out);
+
+/* Release a handle (NULL is ignored). No decode may be in flight on it. */
+void ldpc_code_destroy(ldpc_code *code);
+
+/* Sizes of a code: n = nb*z variable nodes, m = mb*z checks, n_edges = n_blocks*z;
+ * has_4cycles = 1 if two base rows and two base columns close a length-4 cycle
+ * after lifting. Any output pointer may be NULL. */
+int ldpc_code_dims(const ldpc_code *code, int32_t *n, int32_t *m, int64_t *n_edges,
+                   int32_t *n_blocks, int32_t *has_4cycles);
+
+/* Decode a batch of frames.
+ * syndromes: DEVICE uint8 [n_frames][ceil(m/8)], Alice's s = Hx, packed.
+ * llr_in:    DEVICE int8 [n_frames][n], Bob's channel soft values, positive =
+ *            bit 0; -128 is read as -127.
+ * max_iter:  iteration limit (>= 0). The syndrome is tested before the first
+ *            iteration and after each one; 0 runs the test only.
+ * out_bits:  DEVICE uint8 [n_frames][ceil(n/8)], hard decisions [E_j < 0], packed.
+ * out_converged: DEVICE uint8 [n_frames], 1 iff H x^ = s.
+ * n_frames = 0 is a no-op. May allocate a stream-ordered workspace for codes
+ * whose state does not fit on chip (see ldpc_workspace_bytes). */
+int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
+                      int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
+                      uint8_t *out_converged, void *stream);
+
+/* As ldpc_decode_batch, plus optional outputs (each may be NULL):
+ * out_iters: DEVICE int32 [n_frames]: iterations run (0 = converged at the
+ *            pre-check; max_iter when not converged).
+ * out_L:     DEVICE int8 [n_frames][n_blocks][z]: final CN->VN messages, blocks
+ *            in row-major base order, row r of the block at index r.
+ * out_E:     DEVICE int16 [n_frames][n]: final soft values.
+ * workspace: DEVICE buffer of at least ldpc_workspace_bytes(code, n_frames)
+ *            bytes (may be NULL when that size is 0); no allocation happens
+ *            when it is given. */
+int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
+                         int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
+                         uint8_t *out_converged, int32_t *out_iters, int8_t *out_L,
+                         int16_t *out_E, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Device workspace needed by a decode of n_frames frames (0 when the whole
+ * decoder state stays in on-chip memory). Returns 0 for invalid arguments. */
+size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t n_frames);
+
+/* Alice's side of the syndrome exchange: out_syn = H bits for a batch.
+ * bits: DEVICE uint8 [n_frames][ceil(n/8)] packed; out_syn: DEVICE uint8
+ * [n_frames][ceil(m/8)] packed. */
+int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames,
+                        uint8_t *out_syn, void *stream);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *ldpc_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int ldpc_version(void);
+
+/* Host-side self description of the kernels' check-node arithmetic: writes
+ * tau(p, q) of Alg. 1 for p, q in [0, 63] (MSG_max = 63) into out[64 * 64],
+ * computed by the same inline function the GPU kernels use, compiled for the
+ * host. HOST pointer. For testing the kernels' arithmetic without a GPU. */
+int ldpc_host_tau_table(int32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QKDLDPC_H */

@@ -1,0 +1,245 @@
+"""Thin Python binding of libqkdldpc.so (include/qkdldpc.h).
+
+Argument marshalling only: every step of decoding runs in the library's HIP
+kernels. Tensors are torch tensors on the GPU (device pointers); the binding
+checks their dtype, device, contiguity and shape on the host before any call,
+so that a kernel never runs on buffers smaller than it assumes. The library is
+required: when it is not built, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqkdldpc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qkdldpc.h")
+
+LDPC_OK = 0
+LDPC_EINVAL = -1
+LDPC_ENOMEM = -2
+LDPC_EDEVICE = -3
+LDPC_EUNSUPPORTED = -4
+
+LDPC_RULE_RCBP_FB = 0
+LDPC_RULE_RCBP_EQ7 = 1
+LDPC_RULE_MINSUM = 2
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class ldpc_params(C.Structure):
+    _fields_ = [("msg_max", C.c_int32), ("e_max", C.c_int32), ("acc_bits", C.c_int32),
+                ("cn_rule", C.c_int32), ("offsets", C.c_void_p), ("offset_iters", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1903_10107_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ldpc_code_create.restype = C.c_int
+        L.ldpc_code_create.argtypes = [vp, i32, i32, i32, C.POINTER(ldpc_params), C.POINTER(vp)]
+        L.ldpc_code_destroy.restype = None
+        L.ldpc_code_destroy.argtypes = [vp]
+        L.ldpc_code_dims.restype = C.c_int
+        L.ldpc_code_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
+                                     C.POINTER(i32)]
+        L.ldpc_decode_batch.restype = C.c_int
+        L.ldpc_decode_batch.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+        L.ldpc_decode_batch_ex.restype = C.c_int
+        L.ldpc_decode_batch_ex.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.ldpc_workspace_bytes.restype = C.c_size_t
+        L.ldpc_workspace_bytes.argtypes = [vp, i32]
+        L.ldpc_syndrome_batch.restype = C.c_int
+        L.ldpc_syndrome_batch.argtypes = [vp, vp, i32, vp, vp]
+        L.ldpc_last_error.restype = C.c_char_p
+        L.ldpc_last_error.argtypes = []
+        L.ldpc_version.restype = C.c_int
+        L.ldpc_version.argtypes = []
+        L.ldpc_host_tau_table.restype = C.c_int
+        L.ldpc_host_tau_table.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/qkdldpc.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ldpc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _check(rc: int):
+    if rc != LDPC_OK:
+        raise LdpcError(rc, lib().ldpc_last_error().decode())
+
+
+def ldpc_last_error() -> str:
+    return lib().ldpc_last_error().decode()
+
+
+def ldpc_version() -> int:
+    return lib().ldpc_version()
+
+
+def ldpc_host_tau_table() -> np.ndarray:
+    out = np.zeros((64, 64), dtype=np.int32)
+    _check(lib().ldpc_host_tau_table(out.ctypes.data))
+    return out
+
+
+class Code:
+    """A QC-LDPC code handle (ldpc_code_create / ldpc_code_destroy)."""
+
+    def __init__(self, base, z: int, *, msg_max: int = 0, e_max: int = 0, acc_bits: int = 0,
+                 cn_rule: int = LDPC_RULE_RCBP_FB, offsets=None):
+        self._h = None
+        base = np.ascontiguousarray(base, dtype=np.int32)
+        if base.ndim != 2:
+            raise ValueError("base must be a 2-D array")
+        self.base = base
+        self.z = int(z)
+        self._offsets = None
+        prm = ldpc_params(msg_max, e_max, acc_bits, cn_rule, None, 0)
+        if offsets is not None:
+            self._offsets = np.ascontiguousarray(offsets, dtype=np.int8)
+            if self._offsets.ndim != 2 or self._offsets.shape[1] != int((base >= 0).sum()):
+                raise ValueError("offsets must be [offset_iters, n_blocks]")
+            prm.offsets = self._offsets.ctypes.data
+            prm.offset_iters = self._offsets.shape[0]
+        h = C.c_void_p()
+        _check(lib().ldpc_code_create(base.ctypes.data, base.shape[0], base.shape[1], self.z, C.byref(prm),
+                                      C.byref(h)))
+        self._h = h
+        self.acc_bits = acc_bits or 8
+        n, m, nb = C.c_int32(), C.c_int32(), C.c_int32()
+        ne, h4 = C.c_int64(), C.c_int32()
+        _check(lib().ldpc_code_dims(h, C.byref(n), C.byref(m), C.byref(ne), C.byref(nb), C.byref(h4)))
+        self.n, self.m, self.n_edges, self.n_blocks = n.value, m.value, ne.value, nb.value
+        self.has_4cycles = bool(h4.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ldpc_code_destroy(self._h)
+            self._h = None
+
+
+def _dev_ptr(t, dtype, shape, name):
+    """Host-side check of a device tensor before its pointer goes to a kernel."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < int(np.prod(shape)):
+        raise ValueError(f"{name} has {t.numel()} elements; needs {int(np.prod(shape))} ({shape})")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def ldpc_workspace_bytes(code: Code, n_frames: int) -> int:
+    return int(lib().ldpc_workspace_bytes(code.handle, int(n_frames)))
+
+
+def ldpc_decode_batch_ex(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
+                         out_iters=None, out_L=None, out_E=None, workspace=None, stream=None):
+    import torch
+    F = int(n_frames)
+    sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+    if F < 0:
+        raise ValueError("n_frames < 0")
+    if F == 0:
+        return
+    p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+    p_llr = _dev_ptr(llr_in, torch.int8, (F, code.n), "llr_in")
+    p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
+    p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
+    p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
+    p_L = _dev_ptr(out_L, torch.int8, (F, code.n_blocks, code.z), "out_L")
+    p_E = _dev_ptr(out_E, torch.int16, (F, code.n), "out_E")
+    need = ldpc_workspace_bytes(code, F)
+    p_ws, ws_bytes = None, 0
+    if workspace is not None:
+        p_ws = _dev_ptr(workspace, torch.uint8, (need,), "workspace")
+        ws_bytes = workspace.numel()
+    _check(lib().ldpc_decode_batch_ex(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, p_it, p_L, p_E,
+                                      p_ws, ws_bytes, _stream_ptr(stream)))
+
+
+def ldpc_decode_batch(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
+                      stream=None):
+    import torch
+    F = int(n_frames)
+    if F < 0:
+        raise ValueError("n_frames < 0")
+    if F == 0:
+        return
+    sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+    p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+    p_llr = _dev_ptr(llr_in, torch.int8, (F, code.n), "llr_in")
+    p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
+    p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
+    _check(lib().ldpc_decode_batch(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, _stream_ptr(stream)))
+
+
+def ldpc_syndrome_batch(code: Code, bits, n_frames: int, out_syn, stream=None):
+    import torch
+    F = int(n_frames)
+    if F <= 0:
+        if F < 0:
+            raise ValueError("n_frames < 0")
+        return
+    p_b = _dev_ptr(bits, torch.uint8, (F, (code.n + 7) // 8), "bits")
+    p_s = _dev_ptr(out_syn, torch.uint8, (F, (code.m + 7) // 8), "out_syn")
+    _check(lib().ldpc_syndrome_batch(code.handle, p_b, F, p_s, _stream_ptr(stream)))
+
+
+def decode(code: Code, syn, llr, max_iter: int, *, want_state: bool = False, device: str = "cuda"):
+    """numpy in, numpy out: uploads, decodes on the GPU, downloads."""
+    import torch
+    syn = np.ascontiguousarray(syn, dtype=np.uint8)
+    llr = np.ascontiguousarray(llr, dtype=np.int8)
+    F = llr.shape[0]
+    d_syn = torch.from_numpy(syn).to(device)
+    d_llr = torch.from_numpy(llr).to(device)
+    bits = torch.zeros((F, (code.n + 7) // 8), dtype=torch.uint8, device=device)
+    conv = torch.zeros(F, dtype=torch.uint8, device=device)
+    iters = torch.zeros(F, dtype=torch.int32, device=device)
+    L = torch.zeros((F, code.n_blocks, code.z), dtype=torch.int8, device=device) if want_state else None
+    E = torch.zeros((F, code.n), dtype=torch.int16, device=device) if want_state else None
+    ldpc_decode_batch_ex(code, d_syn, d_llr, F, max_iter, bits, conv, iters, L, E)
+    torch.cuda.synchronize()
+    out = {"bits": bits.cpu().numpy(), "conv": conv.cpu().numpy(), "iters": iters.cpu().numpy()}
+    if want_state:
+        out["L"], out["E"] = L.cpu().numpy(), E.cpu().numpy()
+    return out

@@ -1,0 +1,305 @@
+// C ABI of the decoder library (declarations and contracts in include/qkdldpc.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/qkdldpc.h"
+#include "decoder.hpp"
+#include "qc_code.hpp"
+#include "rcbp.hpp"
+
+using qkdldpc::DecodeArgs;
+using qkdldpc::DevCode;
+using qkdldpc::HostCode;
+using qkdldpc::LaunchPlan;
+
+struct ldpc_code {
+    HostCode h;
+    int device = -1;
+    int32_t *d_tables = nullptr; // deg[mb] | blk_off[mb] | colbase[n_blocks] | shift[n_blocks]
+    int8_t *d_offsets = nullptr;
+    DevCode dev{};
+    LaunchPlan plan{};
+    size_t ws_frame_bytes = 0, ws_l_off = 0;
+    int lds_e_off = 0, lds_l_off = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(const char *what, hipError_t e)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return LDPC_EDEVICE;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+void make_plan(ldpc_code *c, int lds_limit)
+{
+    const HostCode &h = c->h;
+    const size_t esize = h.acc_bits == 16 ? 2 : 1;
+    LaunchPlan &P = c->plan;
+    P.acc_bits = h.acc_bits;
+    P.cn_rule = h.cn_rule;
+    P.max_deg = h.max_deg;
+    P.threads = (int)std::min<size_t>(1024, round_up((size_t)h.z, 64));
+    const size_t syn_al = round_up((size_t)(h.m + 7) / 8, 16);
+    const size_t e_al = round_up((size_t)h.n * esize, 16);
+    const size_t total = syn_al + e_al + (size_t)h.n_edges;
+    c->lds_e_off = (int)syn_al;
+    c->lds_l_off = (int)(syn_al + e_al);
+    if (total <= (size_t)lds_limit) {
+        P.lds_state = true;
+        P.lds_bytes = total;
+        c->ws_frame_bytes = 0;
+    } else {
+        P.lds_state = false;
+        P.lds_bytes = syn_al;
+        c->ws_l_off = round_up((size_t)h.n * esize, 256);
+        c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.n_edges, 256);
+    }
+}
+
+int check_device(const ldpc_code *code)
+{
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess)
+        return hip_fail("hipGetDevice", e);
+    if (cur != code->device) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "code was created on device %d but device %d is current", code->device, cur);
+        return fail(LDPC_EINVAL, buf);
+    }
+    return LDPC_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, const ldpc_params *params,
+                     ldpc_code **out)
+{
+    if (!out)
+        return fail(LDPC_EINVAL, "ldpc_code_create: out is NULL");
+    *out = nullptr;
+    HostCode h;
+    std::string err;
+    int rc = qkdldpc::build_host_code(base, mb, nb, z, params, h, err);
+    if (rc != LDPC_OK)
+        return fail(rc, err);
+    if (h.n_edges >= (int64_t(1) << 31))
+        return fail(LDPC_EINVAL, "ldpc_code_create: n_blocks * z must be below 2^31");
+
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail("ldpc_code_create: no usable GPU (hipGetDevice)", e);
+    int lds_limit = 0;
+    e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return hip_fail("ldpc_code_create: hipDeviceGetAttribute", e);
+
+    ldpc_code *c = new (std::nothrow) ldpc_code;
+    if (!c)
+        return fail(LDPC_ENOMEM, "ldpc_code_create: out of host memory");
+    c->h = std::move(h);
+    c->device = dev;
+    const HostCode &hc = c->h;
+    const size_t nt = 2 * (size_t)hc.mb + 2 * (size_t)hc.n_blocks;
+    e = hipMalloc(&c->d_tables, nt * sizeof(int32_t));
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail("ldpc_code_create: hipMalloc", e);
+    }
+    std::vector<int32_t> tab;
+    tab.reserve(nt);
+    tab.insert(tab.end(), hc.deg.begin(), hc.deg.end());
+    tab.insert(tab.end(), hc.blk_off.begin(), hc.blk_off.end());
+    tab.insert(tab.end(), hc.colbase.begin(), hc.colbase.end());
+    tab.insert(tab.end(), hc.shift.begin(), hc.shift.end());
+    e = hipMemcpy(c->d_tables, tab.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hc.offsets.empty()) {
+        e = hipMalloc(&c->d_offsets, hc.offsets.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_offsets, hc.offsets.data(), hc.offsets.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        ldpc_code_destroy(c);
+        return hip_fail("ldpc_code_create: uploading tables", e);
+    }
+    DevCode &d = c->dev;
+    d.deg = c->d_tables;
+    d.blk_off = c->d_tables + hc.mb;
+    d.colbase = c->d_tables + 2 * hc.mb;
+    d.shift = c->d_tables + 2 * hc.mb + hc.n_blocks;
+    d.offsets = c->d_offsets;
+    d.offset_iters = hc.offset_iters;
+    d.mb = hc.mb;
+    d.nb = hc.nb;
+    d.z = hc.z;
+    d.n = hc.n;
+    d.m = hc.m;
+    d.n_blocks = hc.n_blocks;
+    d.msg_max = hc.msg_max;
+    d.e_max = hc.e_max;
+    // leave room for the few bytes of static LDS the barrier reductions use
+    make_plan(c, lds_limit - 1024);
+    *out = c;
+    return LDPC_OK;
+}
+
+void ldpc_code_destroy(ldpc_code *code)
+{
+    if (!code)
+        return;
+    if (code->d_tables)
+        (void)hipFree(code->d_tables);
+    if (code->d_offsets)
+        (void)hipFree(code->d_offsets);
+    delete code;
+}
+
+int ldpc_code_dims(const ldpc_code *code, int32_t *n, int32_t *m, int64_t *n_edges, int32_t *n_blocks,
+                   int32_t *has_4cycles)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_code_dims: code is NULL");
+    if (n)
+        *n = code->h.n;
+    if (m)
+        *m = code->h.m;
+    if (n_edges)
+        *n_edges = code->h.n_edges;
+    if (n_blocks)
+        *n_blocks = code->h.n_blocks;
+    if (has_4cycles)
+        *has_4cycles = code->h.has_4cycles;
+    return LDPC_OK;
+}
+
+size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t n_frames)
+{
+    if (!code || n_frames < 0)
+        return 0;
+    return code->ws_frame_bytes * (size_t)n_frames;
+}
+
+int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                         int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, int32_t *out_iters,
+                         int8_t *out_L, int16_t *out_E, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: code is NULL");
+    if (n_frames < 0)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: n_frames < 0");
+    if (max_iter < 0)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: max_iter < 0");
+    if (n_frames == 0)
+        return LDPC_OK;
+    if (!syndromes || !llr_in || !out_bits || !out_converged)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: syndromes, llr_in, out_bits and out_converged must be non-NULL");
+    int rc = check_device(code);
+    if (rc != LDPC_OK)
+        return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t need = ldpc_workspace_bytes(code, n_frames);
+    void *ws = workspace;
+    bool owned = false;
+    if (need > 0) {
+        if (ws && workspace_bytes < need)
+            return fail(LDPC_EINVAL, "ldpc_decode_batch: workspace smaller than ldpc_workspace_bytes()");
+        if (!ws) {
+            hipError_t e = hipMallocAsync(&ws, need, s);
+            if (e != hipSuccess)
+                return hip_fail("ldpc_decode_batch: hipMallocAsync workspace", e);
+            owned = true;
+        }
+    }
+    DecodeArgs A{};
+    A.syn = syndromes;
+    A.llr = llr_in;
+    A.n_frames = n_frames;
+    A.max_iter = max_iter;
+    A.out_bits = out_bits;
+    A.out_conv = out_converged;
+    A.out_iters = out_iters;
+    A.out_L = out_L;
+    A.out_E = out_E;
+    A.ws = static_cast<uint8_t *>(ws);
+    A.ws_frame_bytes = code->ws_frame_bytes;
+    A.ws_l_off = code->ws_l_off;
+    A.syn_bytes = (code->h.m + 7) / 8;
+    A.bit_bytes = (code->h.n + 7) / 8;
+    A.lds_e_off = code->lds_e_off;
+    A.lds_l_off = code->lds_l_off;
+    hipError_t e = qkdldpc::launch_decode(code->plan, code->dev, A, s);
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(ws, s);
+        if (e == hipSuccess)
+            e = e2;
+    }
+    if (e != hipSuccess)
+        return hip_fail("ldpc_decode_batch: kernel launch", e);
+    return LDPC_OK;
+}
+
+int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                      int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, void *stream)
+{
+    return ldpc_decode_batch_ex(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, nullptr,
+                                nullptr, nullptr, nullptr, 0, stream);
+}
+
+int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames, uint8_t *out_syn,
+                        void *stream)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_syndrome_batch: code is NULL");
+    if (n_frames < 0)
+        return fail(LDPC_EINVAL, "ldpc_syndrome_batch: n_frames < 0");
+    if (n_frames == 0)
+        return LDPC_OK;
+    if (!bits || !out_syn)
+        return fail(LDPC_EINVAL, "ldpc_syndrome_batch: bits and out_syn must be non-NULL");
+    int rc = check_device(code);
+    if (rc != LDPC_OK)
+        return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t bb = (code->h.n + 7) / 8, sb = (code->h.m + 7) / 8;
+    for (int32_t f0 = 0; f0 < n_frames; f0 += 65535) {
+        const int nf = std::min<int32_t>(65535, n_frames - f0);
+        hipError_t e = qkdldpc::launch_syndrome(code->dev, bits + (size_t)f0 * bb, nf, out_syn + (size_t)f0 * sb, s);
+        if (e != hipSuccess)
+            return hip_fail("ldpc_syndrome_batch: kernel launch", e);
+    }
+    return LDPC_OK;
+}
+
+const char *ldpc_last_error(void) { return g_err.c_str(); }
+
+int ldpc_version(void) { return 100; }
+
+int ldpc_host_tau_table(int32_t *out)
+{
+    if (!out)
+        return fail(LDPC_EINVAL, "ldpc_host_tau_table: out is NULL");
+    for (int p = 0; p < 64; ++p)
+        for (int q = 0; q < 64; ++q)
+            out[p * 64 + q] = qkdldpc::tau(p, q);
+    return LDPC_OK;
+}
+
+} // extern "C"

@@ -314,7 +314,7 @@ WORKLOADS = {
     "n1024_q1": Workload("n1024_q1", 5, 32, 32, 64, 0.01, 50),
     # realistic length, QBER 2%: 5x32 base, Z = 1024 (n = 32768, R = 27/32);
     # shortened so that the frame error rate is at most 1e-2
-    "n32768_q2": Workload("n32768_q2", 5, 32, 1024, 256, 0.02, 50, 8, 0.25),
+    "n32768_q2": Workload("n32768_q2", 5, 32, 1024, 256, 0.02, 50, 8, 0.33),
     # literal rate 27/32 at QBER 2% (above the BP threshold: FER near 1)
     "n32768_q2_literal": Workload("n32768_q2_literal", 5, 32, 1024, 256, 0.02, 50),
     # learned-offset workload: 5x32 base, Z = 256 (n = 8192)

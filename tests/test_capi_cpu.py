@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, rejects invalid arguments on the host (before any device
+work), and its check-node arithmetic (compiled for the host from the same
+inline function the kernels use) equals the oracle's Alg. 1 table."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_10107_amd import binding as B
+from paper_1903_10107_amd import inputs as I
+
+
+def test_library_exports_every_declared_function():
+    names = B.header_functions()
+    assert "ldpc_code_create" in names and "ldpc_decode_batch" in names
+    lib = B.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_host_tau_table_equals_oracle_alg1():
+    assert np.array_equal(B.ldpc_host_tau_table(), O.tau_table(64))
+
+
+def test_version():
+    assert B.ldpc_version() >= 100
+
+
+def _create(base, mb, nb, z, prm=None):
+    h = C.c_void_p()
+    base = np.ascontiguousarray(base, dtype=np.int32)
+    rc = B.lib().ldpc_code_create(base.ctypes.data, mb, nb, z, C.byref(prm) if prm else None, C.byref(h))
+    return rc, h
+
+
+GOOD = I.make_base(5, 32, 32)
+
+
+@pytest.mark.parametrize("case", [
+    "null_base", "z0", "mb_ge_nb", "shift_high", "shift_low", "zero_col", "row_deg1", "bad_acc",
+    "bad_msg", "bad_emax", "bad_rule", "off_iters0", "iters_no_off",
+])
+def test_create_rejects_invalid_arguments(case):
+    base = GOOD.copy()
+    mb, nb, z = 5, 32, 32
+    prm = None
+    if case == "null_base":
+        h = C.c_void_p()
+        assert B.lib().ldpc_code_create(None, mb, nb, z, None, C.byref(h)) == B.LDPC_EINVAL
+        return
+    if case == "z0":
+        z = 0
+    elif case == "mb_ge_nb":
+        base, mb, nb = GOOD[:, :5].copy(), 5, 5
+    elif case == "shift_high":
+        base[0, 0] = 32
+    elif case == "shift_low":
+        base[0, 0] = -2
+    elif case == "zero_col":
+        base[:, 3] = -1
+    elif case == "row_deg1":
+        base = np.full((2, 4), -1, np.int32)
+        base[0, :] = 0
+        base[1, 0] = 1
+        mb, nb = 2, 4
+    elif case == "bad_acc":
+        prm = B.ldpc_params(0, 0, 12, 0, None, 0)
+    elif case == "bad_msg":
+        prm = B.ldpc_params(200, 0, 0, 0, None, 0)
+    elif case == "bad_emax":
+        prm = B.ldpc_params(0, 300, 8, 0, None, 0)
+    elif case == "bad_rule":
+        prm = B.ldpc_params(0, 0, 0, 7, None, 0)
+    elif case == "off_iters0":
+        off = np.zeros(96, np.int8)
+        prm = B.ldpc_params(0, 0, 0, 0, off.ctypes.data, 0)
+    elif case == "iters_no_off":
+        prm = B.ldpc_params(0, 0, 0, 0, None, 3)
+    rc, h = _create(base, mb, nb, z, prm)
+    assert rc == B.LDPC_EINVAL
+    assert not h.value
+    assert B.ldpc_last_error()
+
+
+def test_create_rejects_too_high_row_degree_as_unsupported():
+    base = np.zeros((2, 40), np.int32)
+    rc, _ = _create(base, 2, 40, 7)
+    assert rc == B.LDPC_EUNSUPPORTED
+    assert "32" in B.ldpc_last_error()
+
+
+def test_null_out_and_null_code_are_rejected():
+    base = np.ascontiguousarray(GOOD)
+    assert B.lib().ldpc_code_create(base.ctypes.data, 5, 32, 32, None, None) == B.LDPC_EINVAL
+    assert B.lib().ldpc_decode_batch(None, None, None, 1, 1, None, None, None) == B.LDPC_EINVAL
+    assert B.lib().ldpc_decode_batch_ex(None, None, None, 1, 1, None, None, None, None, None, None, 0,
+                                        None) == B.LDPC_EINVAL
+    assert B.lib().ldpc_code_dims(None, None, None, None, None, None) == B.LDPC_EINVAL
+    assert B.lib().ldpc_syndrome_batch(None, None, 1, None, None) == B.LDPC_EINVAL
+    assert B.lib().ldpc_workspace_bytes(None, 4) == 0
+    B.lib().ldpc_code_destroy(None)
+
+
+def test_valid_code_without_a_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h = _create(GOOD, 5, 32, 32)
+    assert rc == B.LDPC_EDEVICE
+    assert not h.value
+    with pytest.raises(B.LdpcError):
+        B.Code(GOOD, 32)

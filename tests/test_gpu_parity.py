@@ -1,0 +1,162 @@
+"""GPU decoder vs the CPU oracle, element by element, through the C ABI.
+
+Every case compares the packed hard decisions, the converged flags, the
+iteration counts, the final CN->VN messages L and the final soft values E,
+bit-exactly. Small cases decode every frame on both sides; the full-size
+workloads decode the whole batch on the GPU in the benchmark's launch
+configuration and compare a sample of frames with the oracle, plus H x^ = s
+on every converged frame.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_10107_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1903_10107_amd import binding
+    binding.lib()
+    return binding
+
+
+def _rand_base(mb, nb, z, seed, col_weight=3):
+    return I.make_base(mb, nb, z, col_weight, seed)
+
+
+CASES = {
+    # name: (base factory, z, frames, qber, max_iter, kwargs for code, frame kwargs)
+    "n1024_q1": (lambda: I.make_base(5, 32, 32), 32, 64, 0.01, 50, {}, {}),
+    "n1024_q3": (lambda: I.make_base(5, 32, 32), 32, 32, 0.03, 50, {}, {}),
+    "array_n20": (lambda: I.array_code_base(5, 3, 4), 5, 16, 0.05, 30, {}, {}),
+    "odd_z37": (lambda: _rand_base(4, 12, 37, 5), 37, 16, 0.03, 40, {}, {}),
+    "n8192_q2": (lambda: I.make_base(5, 32, 256), 256, 16, 0.02, 20, {}, {}),
+    "n32768_short": (lambda: I.make_base(5, 32, 1024), 1024, 6, 0.02, 50, {}, {"short_frac": 0.3}),
+    "z1500_rows_per_thread_2": (lambda: _rand_base(3, 8, 1500, 6), 1500, 4, 0.03, 30, {}, {}),
+    "acc16": (lambda: I.make_base(5, 32, 256), 256, 8, 0.02, 30, {"acc_bits": 16}, {}),
+    "acc8_emax100": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30, {"e_max": 100}, {}),
+    "msgmax31": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30, {"msg_max": 31}, {}),
+    "rule_eq7": (lambda: I.make_base(5, 32, 32), 32, 16, 0.02, 30, {"cn_rule": 1}, {}),
+    "rule_minsum": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2}, {}),
+    "minsum_offsets": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2, "offsets": "rand"}, {}),
+    "rcbp_offsets": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"offsets": "rand"}, {}),
+    "deg6_n98304_global_state": (lambda: I.make_base(24, 48, 2048), 2048, 2, 0.04, 8, {},
+                                 {"short_frac": 0.1, "punct_frac": 0.1}),
+    "max_iter0": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 0, {}, {}),
+    "zero_error": (lambda: I.make_base(5, 32, 32), 32, 8, 1e-9, 50, {}, {}),
+    "row_deg_24": (lambda: _rand_base(2, 24, 64, 7, 2), 64, 8, 0.01, 30, {}, {}),
+}
+
+
+def _frames(base, z, F, q, fkw, seed):
+    code = I.Code(base, z)
+    ns = int(fkw.get("short_frac", 0) * code.n)
+    npn = int(fkw.get("punct_frac", 0) * code.n)
+    return code, I.make_frames(code, F, q, seed, n_short=ns, n_punct=npn)
+
+
+def _compare(got, ref, frames=None):
+    for k in ("bits", "conv", "iters", "L", "E"):
+        if k not in ref:
+            continue
+        g = got[k] if frames is None else got[k][frames]
+        assert g.shape == ref[k].shape, k
+        if not np.array_equal(g, ref[k]):
+            bad = np.argwhere(g != ref[k])
+            raise AssertionError(f"{k} differs at {len(bad)} places, first {bad[:5].tolist()}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity_small(B, name):
+    mk, z, F, q, it, ckw, fkw = CASES[name]
+    base = mk()
+    code, fr = _frames(base, z, F, q, fkw, seed=zlib.crc32(name.encode()) & 0xFFFF)
+    ckw = dict(ckw)
+    okw = {}
+    if ckw.get("offsets") == "rand":
+        rng = np.random.default_rng(1)
+        ckw["offsets"] = rng.integers(0, 4, size=(3, code.n_blocks)).astype(np.int8)
+    if "offsets" in ckw:
+        okw["offsets"] = ckw["offsets"]
+    for k in ("acc_bits", "e_max", "msg_max", "cn_rule"):
+        if k in ckw:
+            okw[k] = ckw[k]
+    _say(f"[gpu parity] {name}: n={code.n} F={F} q={q} max_iter={it} {sorted(okw)}")
+    gc = B.Code(base, z, **ckw)
+    got = B.decode(gc, fr.syn, fr.llr, it, want_state=True)
+    ref = O.decode(base, z, fr.syn, fr.llr, it, want_state=True, **okw)
+    _compare(got, ref)
+
+
+def test_n_frames_zero_is_a_noop(B):
+    import torch
+    code = B.Code(I.make_base(5, 32, 32), 32)
+    e = torch.empty(0, dtype=torch.uint8, device="cuda")
+    B.ldpc_decode_batch(code, e, e.to(torch.int8), 0, 10, e, e)
+    torch.cuda.synchronize()
+
+
+def test_binding_rejects_short_buffers(B):
+    import torch
+    code = B.Code(I.make_base(5, 32, 32), 32)
+    syn = torch.zeros((4, code.m // 8), dtype=torch.uint8, device="cuda")
+    llr = torch.zeros((3, code.n), dtype=torch.int8, device="cuda")
+    bits = torch.zeros((4, code.n // 8), dtype=torch.uint8, device="cuda")
+    conv = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        B.ldpc_decode_batch(code, syn, llr, 4, 10, bits, conv)
+
+
+def test_syndrome_encoder_matches_generator(B):
+    import torch
+    for (mb, nb, z) in ((5, 32, 32), (4, 12, 37), (5, 32, 1024)):
+        base = I.make_base(mb, nb, z, 3, 11)
+        code = I.Code(base, z)
+        fr = I.make_frames(code, 5, 0.05, 12)
+        gc = B.Code(base, z)
+        _say(f"[gpu syndrome] n={code.n}")
+        xb = torch.from_numpy(I.pack_bits(fr.x)).cuda()
+        out = torch.zeros((5, (code.m + 7) // 8), dtype=torch.uint8, device="cuda")
+        B.ldpc_syndrome_batch(gc, xb, 5, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), fr.syn)
+
+
+def _full_size(B, wl_name, sample, seed=10107):
+    wl = I.WORKLOADS[wl_name]
+    code = wl.code()
+    fr = I.make_frames(code, wl.frames, wl.qber, seed, n_short=int(wl.short_frac * code.n))
+    gc = B.Code(code.base, code.z, acc_bits=wl.acc_bits)
+    _say(f"[gpu parity full] {wl_name}: n={code.n} F={wl.frames} max_iter={wl.max_iter}")
+    got = B.decode(gc, fr.syn, fr.llr, wl.max_iter, want_state=True)
+    _say(f"[gpu parity full] {wl_name}: gpu done, conv={got['conv'].mean():.3f}")
+    # every converged frame satisfies H x^ = s (H applied by the generator, not the decoder)
+    xh = I.unpack_bits(got["bits"], code.n)
+    s_ok = (I.pack_bits(I.syndrome_bits(code, xh)) == fr.syn).all(1)
+    assert np.array_equal(s_ok, got["conv"].astype(bool))
+    ref = O.decode(code.base, code.z, fr.syn[sample], fr.llr[sample], wl.max_iter, want_state=True,
+                   acc_bits=wl.acc_bits)
+    _compare(got, ref, frames=sample)
+    return got
+
+
+def test_parity_full_n32768_sampled(B):
+    got = _full_size(B, "n32768_q2", sample=np.array([0, 1, 37, 101, 128, 200, 254, 255]))
+    assert got["conv"].mean() > 0.9
+
+
+def test_parity_full_n1048576_sampled(B):
+    _full_size(B, "n1048576_q2", sample=np.array([0, 31]))
