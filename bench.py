@@ -64,19 +64,67 @@ def cpu_baseline(code, fr, wl, seconds: float):
 
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     threads = max(1, min(threads, O.max_threads() if threads <= 0 else threads))
-    done, bits_ok, elapsed = 0, 0, 0.0
-    while done < fr.n_frames and elapsed < seconds:
-        sl = slice(done, min(done + threads, fr.n_frames))
+    done, bits_ok, elapsed, passes = 0, 0, 0.0, 0
+    # whole chunks of `threads` frames, cycling over the batch until `seconds` of decoding
+    while elapsed < seconds:
+        start = done % fr.n_frames
+        sl = slice(start, min(start + threads, fr.n_frames))
         t = time.perf_counter()
         r = O.decode(code.base, code.z, fr.syn[sl], fr.llr[sl], wl.max_iter, acc_bits=wl.acc_bits,
                      n_threads=threads)
         elapsed += time.perf_counter() - t
         ok, _ = M.frame_outcomes(fr.x[sl], I.unpack_bits(r["bits"], code.n), r["conv"])
         bits_ok += int(fr.key_bits()[sl][ok].sum())
-        done = sl.stop
+        done += sl.stop - sl.start
     return {"value": round(bits_ok / elapsed / 1e6, 3), "unit": "Mbit/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} of the {fr.n_frames} frames of the same workload, oracle with {threads} "
-                      f"OpenMP threads over frames, {elapsed:.1f} s"}
+            "sample": f"{done} frame decodes cycling over the {fr.n_frames} frames of the same workload "
+                      f"(oracle, {threads} OpenMP threads over frames, {elapsed:.1f} s of decoding)"}
+
+
+def copy_calibration(nbytes: int, steps: int, warmup: int):
+    """A plain device-to-device copy of a known size: its FETCH_SIZE and
+    WRITE_SIZE counters give the factor that turns counter readings into bytes."""
+    import torch
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    print(json.dumps({"copy_bytes": nbytes, "ms_per_copy": round(ms, 4),
+                      "read_plus_write_GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}), flush=True)
+
+
+def fer_sweep(wl, code, fracs, n_frames: int):
+    """Frame error rate, iterations and efficiency at several shortened
+    fractions of the workload's code and QBER, decoding n_frames per point."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+
+    torch.cuda.set_device(0)
+    gc = B.Code(code.base, code.z, acc_bits=wl.acc_bits)
+    for frac in fracs:
+        ns = int(round(frac * code.n))
+        fr = I.make_frames(code, n_frames, wl.qber, 777, n_short=ns)
+        got = B.decode(gc, fr.syn, fr.llr, wl.max_iter)
+        ok, und = M.frame_outcomes(fr.x, I.unpack_bits(got["bits"], code.n), got["conv"])
+        fails = int(n_frames - ok.sum())
+        lo, hi = M.wilson_interval(fails, n_frames)
+        f_eff = float(np.mean(M.efficiency(code.n, code.m, fr.n_punct, fr.n_short, fr.qber)))
+        print(json.dumps({"workload": wl.name, "short_frac": frac, "shortened": ns, "frames": n_frames,
+                          "fer": fails / n_frames, "fer_ci95": [round(lo, 5), round(hi, 5)],
+                          "undetected": int(und.sum()), "mean_iters": round(float(got["iters"].mean()), 3),
+                          "p99_iters": float(np.percentile(got["iters"], 99)),
+                          "efficiency_f": round(f_eff, 4)}), flush=True)
 
 
 def main():
@@ -87,6 +135,12 @@ def main():
     ap.add_argument("--workload", default="n32768_q2")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fer-sweep", default="",
+                    help="comma-separated shortened fractions: print FER, iterations and f at each")
+    ap.add_argument("--sweep-frames", type=int, default=4096)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="instead of decoding, run a plain device copy of BYTES bytes per step "
+                         "(reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: frames are independent, so N GPUs would each decode their own "
@@ -99,8 +153,14 @@ def main():
     from paper_1903_10107_amd import inputs as I
     from paper_1903_10107_amd import metrics as M
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, args.steps, args.warmup)
+        return
     wl = I.WORKLOADS[args.workload]
     code = wl.code()
+    if args.fer_sweep:
+        fer_sweep(wl, code, [float(v) for v in args.fer_sweep.split(",")], args.sweep_frames)
+        return
     n_short = int(round(wl.short_frac * code.n))
     fr = I.make_frames(code, wl.frames, wl.qber, 10107, n_short=n_short)
     torch.cuda.set_device(0)

@@ -142,6 +142,14 @@ int ldpc_version(void);
  * host. HOST pointer. For testing the kernels' arithmetic without a GPU. */
 int ldpc_host_tau_table(int32_t *out);
 
+/* Host-side self description of the packed check-node fold of the GPU kernels
+ * (two rows per 32-bit register, rows shorter than 32 padded with a neutral
+ * operand): for a row of degree d in 2..32 and clipped input magnitudes in
+ * 0..127, writes the output magnitude for every edge under the given rule, for
+ * the two rows held in the low and high halves. HOST pointers, length d. */
+int ldpc_host_fold_pair(int32_t rule, const int32_t *p_lo, const int32_t *p_hi, int32_t d,
+                        int32_t *out_lo, int32_t *out_hi);
+
 #ifdef __cplusplus
 }
 #endif

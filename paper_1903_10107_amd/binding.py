@@ -72,6 +72,8 @@ def lib():
         L.ldpc_version.argtypes = []
         L.ldpc_host_tau_table.restype = C.c_int
         L.ldpc_host_tau_table.argtypes = [vp]
+        L.ldpc_host_fold_pair.restype = C.c_int
+        L.ldpc_host_fold_pair.argtypes = [i32, vp, vp, i32, vp, vp]
         _lib = L
     return _lib
 

@@ -19,12 +19,12 @@ using qkdldpc::LaunchPlan;
 struct ldpc_code {
     HostCode h;
     int device = -1;
-    int32_t *d_tables = nullptr; // deg[mb] | blk_off[mb] | colbase[n_blocks] | shift[n_blocks]
-    int8_t *d_offsets = nullptr;
+    int32_t *d_tables = nullptr; // deg[mb] | blk_off[mb] | colbase | shift | colshift [n_blocks each]
+    int32_t *d_offsets = nullptr;
     DevCode dev{};
     LaunchPlan plan{};
     size_t ws_frame_bytes = 0, ws_l_off = 0;
-    int lds_e_off = 0, lds_l_off = 0;
+    int lds_e_off = 0, lds_l_off = 0, lds_syn_off = 0, lds_flag_off = 0, l_stride = 0;
 };
 
 namespace {
@@ -52,20 +52,42 @@ void make_plan(ldpc_code *c, int lds_limit)
     LaunchPlan &P = c->plan;
     P.acc_bits = h.acc_bits;
     P.cn_rule = h.cn_rule;
+    P.min_deg = h.min_deg;
     P.max_deg = h.max_deg;
     P.threads = (int)std::min<size_t>(1024, round_up((size_t)h.z, 64));
-    const size_t syn_al = round_up((size_t)(h.m + 7) / 8, 16);
+    // Scalar kernel LDS layout: E at offset 0, L [block][row], the syndrome.
+    const size_t syn_bytes = (size_t)(h.m + 7) / 8;
     const size_t e_al = round_up((size_t)h.n * esize, 16);
-    const size_t total = syn_al + e_al + (size_t)h.n_edges;
-    c->lds_e_off = (int)syn_al;
-    c->lds_l_off = (int)(syn_al + e_al);
-    if (total <= (size_t)lds_limit) {
+    const size_t l_al = round_up((size_t)h.n_edges, 16);
+    const size_t total = e_al + l_al + syn_bytes;
+    c->lds_e_off = 0;
+    c->lds_l_off = (int)e_al;
+    c->lds_syn_off = (int)(e_al + l_al);
+    P.pow2 = (h.z & (h.z - 1)) == 0;
+    P.pairs = false;
+    // Packed kernel LDS layout: E at offset 0, L as [pair][block][half] with an
+    // odd-dword stride per pair, the syndrome, two flag words.
+    const size_t stride = (((2 * (size_t)h.n_blocks + 3) / 4) | 1) * 4;
+    const size_t lp_al = round_up((size_t)(h.z / 2) * stride, 16);
+    const size_t total_x2 = e_al + lp_al + round_up(syn_bytes, 16) + 16;
+    if (h.z % 2 == 0 && total_x2 <= (size_t)lds_limit) {
+        P.pairs = true;
+        P.lds_state = true;
+        P.lds_bytes = total_x2;
+        P.threads = (int)std::min<size_t>(512, round_up((size_t)h.z / 2, 64));
+        c->l_stride = (int)stride;
+        c->lds_l_off = (int)e_al;
+        c->lds_syn_off = (int)(e_al + lp_al);
+        c->lds_flag_off = (int)(e_al + lp_al + round_up(syn_bytes, 16));
+        c->ws_frame_bytes = 0;
+    } else if (total <= (size_t)lds_limit) {
         P.lds_state = true;
         P.lds_bytes = total;
         c->ws_frame_bytes = 0;
     } else {
         P.lds_state = false;
-        P.lds_bytes = syn_al;
+        P.lds_bytes = syn_bytes;
+        c->lds_syn_off = 0;
         c->ws_l_off = round_up((size_t)h.n * esize, 256);
         c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.n_edges, 256);
     }
@@ -118,7 +140,7 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, con
     c->h = std::move(h);
     c->device = dev;
     const HostCode &hc = c->h;
-    const size_t nt = 2 * (size_t)hc.mb + 2 * (size_t)hc.n_blocks;
+    const size_t nt = 2 * (size_t)hc.mb + 3 * (size_t)hc.n_blocks;
     e = hipMalloc(&c->d_tables, nt * sizeof(int32_t));
     if (e != hipSuccess) {
         delete c;
@@ -130,11 +152,14 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, con
     tab.insert(tab.end(), hc.blk_off.begin(), hc.blk_off.end());
     tab.insert(tab.end(), hc.colbase.begin(), hc.colbase.end());
     tab.insert(tab.end(), hc.shift.begin(), hc.shift.end());
+    for (int i = 0; i < hc.n_blocks; ++i)
+        tab.push_back(hc.colbase[i] | hc.shift[i]);
     e = hipMemcpy(c->d_tables, tab.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && !hc.offsets.empty()) {
-        e = hipMalloc(&c->d_offsets, hc.offsets.size());
+        std::vector<int32_t> off32(hc.offsets.begin(), hc.offsets.end());
+        e = hipMalloc(&c->d_offsets, off32.size() * sizeof(int32_t));
         if (e == hipSuccess)
-            e = hipMemcpy(c->d_offsets, hc.offsets.data(), hc.offsets.size(), hipMemcpyHostToDevice);
+            e = hipMemcpy(c->d_offsets, off32.data(), off32.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         ldpc_code_destroy(c);
@@ -145,6 +170,7 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, con
     d.blk_off = c->d_tables + hc.mb;
     d.colbase = c->d_tables + 2 * hc.mb;
     d.shift = c->d_tables + 2 * hc.mb + hc.n_blocks;
+    d.colshift = c->d_tables + 2 * hc.mb + 2 * hc.n_blocks;
     d.offsets = c->d_offsets;
     d.offset_iters = hc.offset_iters;
     d.mb = hc.mb;
@@ -245,6 +271,9 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
     A.bit_bytes = (code->h.n + 7) / 8;
     A.lds_e_off = code->lds_e_off;
     A.lds_l_off = code->lds_l_off;
+    A.lds_syn_off = code->lds_syn_off;
+    A.lds_flag_off = code->lds_flag_off;
+    A.l_stride = code->l_stride;
     hipError_t e = qkdldpc::launch_decode(code->plan, code->dev, A, s);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, s);
@@ -291,6 +320,40 @@ int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_fr
 const char *ldpc_last_error(void) { return g_err.c_str(); }
 
 int ldpc_version(void) { return 100; }
+
+int ldpc_host_fold_pair(int32_t rule, const int32_t *p_lo, const int32_t *p_hi, int32_t d, int32_t *out_lo,
+                        int32_t *out_hi)
+{
+    using qkdldpc::u16x2;
+    constexpr int D = qkdldpc::kMaxRowDegree;
+    if (!p_lo || !p_hi || !out_lo || !out_hi)
+        return fail(LDPC_EINVAL, "ldpc_host_fold_pair: NULL pointer");
+    if (d < 2 || d > D)
+        return fail(LDPC_EINVAL, "ldpc_host_fold_pair: d must be in 2..32");
+    if (rule < LDPC_RULE_RCBP_FB || rule > LDPC_RULE_MINSUM)
+        return fail(LDPC_EINVAL, "ldpc_host_fold_pair: unknown rule");
+    u16x2 p[D], m[D];
+    for (int k = 0; k < D; ++k) {
+        if (k < d) {
+            if (p_lo[k] < 0 || p_lo[k] > 127 || p_hi[k] < 0 || p_hi[k] > 127)
+                return fail(LDPC_EINVAL, "ldpc_host_fold_pair: magnitudes must be in 0..127");
+            p[k] = u16x2{(unsigned short)p_lo[k], (unsigned short)p_hi[k]};
+        } else {
+            p[k] = u16x2{qkdldpc::kPad, qkdldpc::kPad};
+        }
+    }
+    if (rule == LDPC_RULE_MINSUM)
+        qkdldpc::cn_fold_x2<D, qkdldpc::kRuleMinSum>(p, m);
+    else if (rule == LDPC_RULE_RCBP_EQ7)
+        qkdldpc::cn_fold_x2<D, qkdldpc::kRuleRcbpEq7>(p, m);
+    else
+        qkdldpc::cn_fold_x2<D, qkdldpc::kRuleRcbpFB>(p, m);
+    for (int k = 0; k < d; ++k) {
+        out_lo[k] = m[k].x;
+        out_hi[k] = m[k].y;
+    }
+    return LDPC_OK;
+}
 
 int ldpc_host_tau_table(int32_t *out)
 {

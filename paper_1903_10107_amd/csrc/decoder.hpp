@@ -24,15 +24,18 @@ struct DecodeArgs {
     size_t ws_frame_bytes;
     size_t ws_l_off;      // offset of L inside a frame's workspace slice
     int syn_bytes, bit_bytes;
-    int lds_e_off, lds_l_off;
+    int lds_e_off, lds_l_off, lds_syn_off, lds_flag_off;
+    int l_stride;         // packed kernel: bytes between two row pairs' L slices
 };
 
 struct LaunchPlan {
     int acc_bits;
     int cn_rule;
-    int max_deg;
+    int min_deg, max_deg;
     int threads;      // workgroup size, a multiple of 64, <= 1024
     bool lds_state;   // E and L in LDS
+    bool pairs;       // packed kernel: one lane per row pair (r, r + Z/2); needs even Z and LDS state
+    bool pow2;        // Z is a power of two
     size_t lds_bytes; // dynamic LDS per workgroup
 };
 

@@ -100,6 +100,7 @@ int build_host_code(const int32_t *base, int32_t mb, int32_t nb, int32_t z, cons
             return LDPC_EUNSUPPORTED;
         }
         h.max_deg = std::max(h.max_deg, h.deg[b]);
+        h.min_deg = b == 0 ? h.deg[b] : std::min(h.min_deg, h.deg[b]);
     }
     h.n_blocks = (int32_t)h.colbase.size();
     h.n_edges = (int64_t)h.n_blocks * z;

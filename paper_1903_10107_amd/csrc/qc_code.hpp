@@ -21,14 +21,15 @@ struct DevCode {
     const int32_t *blk_off;  // [mb] index of base row b's first block
     const int32_t *colbase;  // [n_blocks] c * Z of each block, row-major block order
     const int32_t *shift;    // [n_blocks] circulant shift of each block
-    const int8_t *offsets;   // [offset_iters][n_blocks] or nullptr
+    const int32_t *colshift; // [n_blocks] c * Z | shift (meaningful when Z is a power of two)
+    const int32_t *offsets;  // [offset_iters][n_blocks] or nullptr (int32 so that reads are scalar loads)
     int32_t offset_iters;
     int32_t mb, nb, z, n, m, n_blocks;
     int32_t msg_max, e_max;
 };
 
 struct HostCode {
-    int32_t mb = 0, nb = 0, z = 0, n = 0, m = 0, n_blocks = 0, max_deg = 0;
+    int32_t mb = 0, nb = 0, z = 0, n = 0, m = 0, n_blocks = 0, min_deg = 0, max_deg = 0;
     int64_t n_edges = 0;
     int32_t has_4cycles = 0;
     int32_t msg_max = 63, e_max = 127, acc_bits = 8, cn_rule = 0, offset_iters = 0;

@@ -112,3 +112,22 @@ def test_valid_code_without_a_gpu_fails_loudly():
     assert not h.value
     with pytest.raises(B.LdpcError):
         B.Code(GOOD, 32)
+
+
+@pytest.mark.parametrize("rule", [O.RULE_RCBP_FB, O.RULE_RCBP_EQ7, O.RULE_MINSUM])
+def test_host_packed_fold_equals_oracle(rule):
+    """The kernels' packed fold (two rows per register, padded to 32 operands)
+    computes the oracle's magnitudes for every degree and rule."""
+    rng = np.random.default_rng(rule + 10)
+    lib = B.lib()
+    for trial in range(400):
+        d = int(rng.integers(2, 33))
+        hi_cap = 127 if trial % 4 == 0 else 63
+        lo = rng.integers(0, 64 if trial % 3 else 8, size=d).astype(np.int32)
+        hi = rng.integers(0, hi_cap + 1, size=d).astype(np.int32)
+        olo = np.zeros(d, np.int32)
+        ohi = np.zeros(d, np.int32)
+        assert lib.ldpc_host_fold_pair(rule, lo.ctypes.data, hi.ctypes.data, d, olo.ctypes.data,
+                                       ohi.ctypes.data) == 0
+        assert np.array_equal(olo, O.cn_magnitudes(lo, rule, msg_max=127))
+        assert np.array_equal(ohi, O.cn_magnitudes(hi, rule, msg_max=127))
