@@ -120,6 +120,16 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
                          uint8_t *out_converged, int32_t *out_iters, int8_t *out_L,
                          int16_t *out_E, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Kernel family the decode calls of a code launch (one workgroup per frame):
+ * LDPC_KERNEL_GLOBAL   state in a global-memory workspace, one lane per row;
+ * LDPC_KERNEL_LDS      state in LDS, one lane per row;
+ * LDPC_KERNEL_PAIRS    state in LDS, one lane per row pair (r, r + z/2), 16-bit packed;
+ * LDPC_KERNEL_SPLIT    state in LDS, two lanes per row pair, 16-bit packed.
+ * Also the workgroup size and the dynamic LDS bytes per workgroup. Any output
+ * pointer may be NULL. */
+enum { LDPC_KERNEL_GLOBAL = 0, LDPC_KERNEL_LDS = 1, LDPC_KERNEL_PAIRS = 2, LDPC_KERNEL_SPLIT = 3 };
+int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int32_t *lds_bytes);
+
 /* Device workspace needed by a decode of n_frames frames (0 when the whole
  * decoder state stays in on-chip memory). Returns 0 for invalid arguments. */
 size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t n_frames);

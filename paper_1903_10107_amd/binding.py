@@ -28,6 +28,8 @@ LDPC_RULE_RCBP_FB = 0
 LDPC_RULE_RCBP_EQ7 = 1
 LDPC_RULE_MINSUM = 2
 
+KERNEL_NAMES = {0: "global", 1: "lds", 2: "pairs", 3: "split"}
+
 
 class LdpcError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -62,6 +64,8 @@ def lib():
         L.ldpc_decode_batch.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
         L.ldpc_decode_batch_ex.restype = C.c_int
         L.ldpc_decode_batch_ex.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.ldpc_code_plan.restype = C.c_int
+        L.ldpc_code_plan.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ldpc_workspace_bytes.restype = C.c_size_t
         L.ldpc_workspace_bytes.argtypes = [vp, i32]
         L.ldpc_syndrome_batch.restype = C.c_int
@@ -137,6 +141,12 @@ class Code:
     @property
     def handle(self):
         return self._h
+
+    def plan(self) -> dict:
+        """Kernel family, workgroup size and dynamic LDS of this code's decodes."""
+        k, t, l = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().ldpc_code_plan(self._h, C.byref(k), C.byref(t), C.byref(l)))
+        return {"kernel": KERNEL_NAMES[k.value], "threads": t.value, "lds_bytes": l.value}
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

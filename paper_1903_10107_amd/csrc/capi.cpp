@@ -21,6 +21,9 @@ struct ldpc_code {
     int device = -1;
     int32_t *d_tables = nullptr; // deg[mb] | blk_off[mb] | colbase | shift | colshift [n_blocks each]
     int32_t *d_offsets = nullptr;
+    void *d_split = nullptr;     // split kernel: lane table [mb][DMAX/2][2] int4, then blk2slot [n_blocks]
+    size_t lane_tab_bytes = 0;
+    int lds_tab_off = 0;
     DevCode dev{};
     LaunchPlan plan{};
     size_t ws_frame_bytes = 0, ws_l_off = 0;
@@ -45,6 +48,36 @@ int hip_fail(const char *what, hipError_t e)
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Per-lane slot table of the split kernel: lane A's slot i is edge i of the
+// layer, lane B's slot i is edge DMAX-1-i; edges past the row degree are
+// padding and point at the dummy block column nb.
+std::vector<int32_t> split_tables(const HostCode &h, int dmax)
+{
+    const int dh = dmax / 2;
+    std::vector<int32_t> t((size_t)h.mb * dh * 2 * 4 + h.n_blocks, 0);
+    int32_t *b2s = t.data() + (size_t)h.mb * dh * 2 * 4;
+    for (int b = 0; b < h.mb; ++b)
+        for (int i = 0; i < dh; ++i)
+            for (int lane = 0; lane < 2; ++lane) {
+                const int g = lane ? dmax - 1 - i : i;
+                int32_t *e = t.data() + (((size_t)b * dh + i) * 2 + lane) * 4;
+                if (g < h.deg[b]) {
+                    const int blk = h.blk_off[b] + g;
+                    e[0] = h.colbase[blk] | h.shift[blk];
+                    e[1] = h.colbase[blk];
+                    e[2] = -1;
+                    e[3] = blk;
+                    b2s[blk] = b * 4 * dh + 2 * i + lane;
+                } else {
+                    e[0] = 0;
+                    e[1] = h.nb * h.z;
+                    e[2] = 0;
+                    e[3] = -1;
+                }
+            }
+    return t;
+}
+
 void make_plan(ldpc_code *c, int lds_limit)
 {
     const HostCode &h = c->h;
@@ -65,6 +98,34 @@ void make_plan(ldpc_code *c, int lds_limit)
     c->lds_syn_off = (int)(e_al + l_al);
     P.pow2 = (h.z & (h.z - 1)) == 0;
     P.pairs = false;
+    P.split_dmax = 0;
+    // Split kernel (two lanes per row pair): power-of-two Z, forward-backward or
+    // min-sum rule, no offsets, row degree <= 20. LDS: E plus a dummy block
+    // column, L as [pair][layer][half][slot][lane] with an odd-dword pair stride,
+    // the syndrome, the lane table, two flag words.
+    if (P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
+        (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM)) {
+        const int dmax = h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
+        const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
+        const size_t stride = (((size_t)h.mb * dh) | 1) * 4;
+        const size_t l_sp = round_up((size_t)(h.z / 2) * stride, 16);
+        const size_t tab = (size_t)h.mb * dh * 2 * 16;
+        const size_t total_sp = e_sp + l_sp + round_up(syn_bytes, 16) + tab + 16;  // three vote words
+        if (total_sp <= (size_t)lds_limit) {
+            P.split_dmax = dmax;
+            P.lds_state = true;
+            P.lds_bytes = total_sp;
+            P.threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
+            c->l_stride = (int)stride;
+            c->lds_l_off = (int)e_sp;
+            c->lds_syn_off = (int)(e_sp + l_sp);
+            c->lds_tab_off = (int)(e_sp + l_sp + round_up(syn_bytes, 16));
+            c->lds_flag_off = (int)(c->lds_tab_off + tab);
+            c->ws_frame_bytes = 0;
+            c->lane_tab_bytes = tab;
+            return;
+        }
+    }
     // Packed kernel LDS layout: E at offset 0, L as [pair][block][half] with an
     // odd-dword stride per pair, the syndrome, two flag words.
     const size_t stride = (((2 * (size_t)h.n_blocks + 3) / 4) | 1) * 4;
@@ -183,6 +244,16 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, con
     d.e_max = hc.e_max;
     // leave room for the few bytes of static LDS the barrier reductions use
     make_plan(c, lds_limit - 1024);
+    if (c->plan.split_dmax) {
+        const std::vector<int32_t> st = split_tables(hc, c->plan.split_dmax);
+        e = hipMalloc(&c->d_split, st.size() * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_split, st.data(), st.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            ldpc_code_destroy(c);
+            return hip_fail("ldpc_code_create: uploading lane tables", e);
+        }
+    }
     *out = c;
     return LDPC_OK;
 }
@@ -195,6 +266,8 @@ void ldpc_code_destroy(ldpc_code *code)
         (void)hipFree(code->d_tables);
     if (code->d_offsets)
         (void)hipFree(code->d_offsets);
+    if (code->d_split)
+        (void)hipFree(code->d_split);
     delete code;
 }
 
@@ -213,6 +286,21 @@ int ldpc_code_dims(const ldpc_code *code, int32_t *n, int32_t *m, int64_t *n_edg
         *n_blocks = code->h.n_blocks;
     if (has_4cycles)
         *has_4cycles = code->h.has_4cycles;
+    return LDPC_OK;
+}
+
+int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int32_t *lds_bytes)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_code_plan: code is NULL");
+    const LaunchPlan &P = code->plan;
+    if (kernel)
+        *kernel = P.split_dmax ? LDPC_KERNEL_SPLIT : P.pairs ? LDPC_KERNEL_PAIRS
+                                                 : P.lds_state ? LDPC_KERNEL_LDS : LDPC_KERNEL_GLOBAL;
+    if (threads)
+        *threads = P.threads;
+    if (lds_bytes)
+        *lds_bytes = (int32_t)P.lds_bytes;
     return LDPC_OK;
 }
 
@@ -274,6 +362,11 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
     A.lds_syn_off = code->lds_syn_off;
     A.lds_flag_off = code->lds_flag_off;
     A.l_stride = code->l_stride;
+    A.lds_tab_off = code->lds_tab_off;
+    A.lane_tab = static_cast<const int4 *>(code->d_split);
+    A.blk2slot = code->d_split ? reinterpret_cast<const int32_t *>(static_cast<const uint8_t *>(code->d_split) +
+                                                                    code->lane_tab_bytes)
+                               : nullptr;
     hipError_t e = qkdldpc::launch_decode(code->plan, code->dev, A, s);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, s);

@@ -25,7 +25,10 @@ struct DecodeArgs {
     size_t ws_l_off;      // offset of L inside a frame's workspace slice
     int syn_bytes, bit_bytes;
     int lds_e_off, lds_l_off, lds_syn_off, lds_flag_off;
-    int l_stride;         // packed kernel: bytes between two row pairs' L slices
+    int l_stride;         // packed kernels: bytes between two row pairs' L slices
+    int lds_tab_off;      // split kernel: per-lane slot table in LDS
+    const int4 *lane_tab; // split kernel: [mb][DMAX/2][2] {c*Z | shift, c*Z, pad mask, block}
+    const int32_t *blk2slot; // split kernel: block -> byte offset of its slot in a row pair's L slice
 };
 
 struct LaunchPlan {
@@ -36,6 +39,7 @@ struct LaunchPlan {
     bool lds_state;   // E and L in LDS
     bool pairs;       // packed kernel: one lane per row pair (r, r + Z/2); needs even Z and LDS state
     bool pow2;        // Z is a power of two
+    int split_dmax;   // split kernel (two lanes per row pair) with this slot count, or 0
     size_t lds_bytes; // dynamic LDS per workgroup
 };
 

@@ -94,11 +94,21 @@ def test_parity_small(B, name):
     for k in ("acc_bits", "e_max", "msg_max", "cn_rule"):
         if k in ckw:
             okw[k] = ckw[k]
-    _say(f"[gpu parity] {name}: n={code.n} F={F} q={q} max_iter={it} {sorted(okw)}")
     gc = B.Code(base, z, **ckw)
+    _say(f"[gpu parity] {name}: n={code.n} F={F} q={q} max_iter={it} {sorted(okw)} {gc.plan()}")
     got = B.decode(gc, fr.syn, fr.llr, it, want_state=True)
     ref = O.decode(base, z, fr.syn, fr.llr, it, want_state=True, **okw)
     _compare(got, ref)
+
+
+def test_cases_cover_every_kernel_family(B):
+    seen = set()
+    for name, (mk, z, F, q, it, ckw, fkw) in CASES.items():
+        ckw = dict(ckw)
+        if ckw.get("offsets") == "rand":
+            ckw["offsets"] = np.zeros((1, int((mk() >= 0).sum())), np.int8)
+        seen.add(B.Code(mk(), z, **ckw).plan()["kernel"])
+    assert seen == {"global", "lds", "pairs", "split"}, seen
 
 
 def test_n_frames_zero_is_a_noop(B):
@@ -140,7 +150,7 @@ def _full_size(B, wl_name, sample, seed=10107):
     code = wl.code()
     fr = I.make_frames(code, wl.frames, wl.qber, seed, n_short=int(wl.short_frac * code.n))
     gc = B.Code(code.base, code.z, acc_bits=wl.acc_bits)
-    _say(f"[gpu parity full] {wl_name}: n={code.n} F={wl.frames} max_iter={wl.max_iter}")
+    _say(f"[gpu parity full] {wl_name}: n={code.n} F={wl.frames} max_iter={wl.max_iter} {gc.plan()}")
     got = B.decode(gc, fr.syn, fr.llr, wl.max_iter, want_state=True)
     _say(f"[gpu parity full] {wl_name}: gpu done, conv={got['conv'].mean():.3f}")
     # every converged frame satisfies H x^ = s (H applied by the generator, not the decoder)
