@@ -45,11 +45,17 @@ def algorithmic_int_ops(code_dims, iters_sum):
     per_iter = 14 * n_edges + 27 * z * sum(d - 2 for d in degs)
     return float(per_iter) * float(iters_sum)
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_1903_10107_amd", "csrc", "decoder.hip")
+CSRC = os.path.join(ROOT, "paper_1903_10107_amd", "csrc")
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of every kernel source and header the decode kernels are built from."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str):

@@ -134,6 +134,43 @@ int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int
  * decoder state stays in on-chip memory). Returns 0 for invalid arguments. */
 size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t n_frames);
 
+/* Batch schedule. A zero-initialised block is one workgroup per frame, placed by
+ * the hardware dispatcher (what ldpc_decode_batch does). */
+typedef struct {
+    int32_t persistent_workgroups; /* > 0: launch that many workgroups; each takes the next
+                                      frame from a device queue until none is left, so a CU that
+                                      finishes a frame starts another at once. Needs the
+                                      LDPC_KERNEL_SPLIT kernel family (ldpc_code_plan). */
+    const int32_t *order;          /* DEVICE int32 [n_frames] or NULL: the order in which the
+                                      queue hands out frames, a permutation of 0..n_frames-1
+                                      (for instance hardest first); out-of-range entries are
+                                      skipped. Only with persistent_workgroups > 0. */
+} ldpc_schedule;
+
+/* ldpc_decode_batch_ex with a schedule (NULL = default). The decoded results do
+ * not depend on the schedule. The workspace must hold
+ * ldpc_workspace_bytes_sched(code, n_frames, sched) bytes (a persistent schedule
+ * needs 256 bytes for its queue); NULL allocates it stream-ordered.
+ * Returns LDPC_EUNSUPPORTED for a persistent schedule on other kernel families. */
+int ldpc_decode_batch_sched(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
+                            int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
+                            uint8_t *out_converged, int32_t *out_iters, const ldpc_schedule *sched,
+                            void *workspace, size_t workspace_bytes, void *stream);
+size_t ldpc_workspace_bytes_sched(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched);
+
+/* A decode of fixed buffers captured once as a HIP graph (the queue reset and the
+ * decode kernel), replayed by ldpc_batch_launch with one graph launch. All
+ * pointers are DEVICE pointers that must stay valid for the life of the batch;
+ * the workspace, when one is needed and not given, is allocated at create and
+ * freed at destroy. The code handle must outlive the batch. */
+typedef struct ldpc_batch ldpc_batch;
+int ldpc_batch_create(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
+                      int32_t n_frames, int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged,
+                      int32_t *out_iters, const ldpc_schedule *sched, void *workspace,
+                      size_t workspace_bytes, ldpc_batch **out);
+int ldpc_batch_launch(ldpc_batch *batch, void *stream);
+void ldpc_batch_destroy(ldpc_batch *batch);
+
 /* Alice's side of the syndrome exchange: out_syn = H bits for a batch.
  * bits: DEVICE uint8 [n_frames][ceil(n/8)] packed; out_syn: DEVICE uint8
  * [n_frames][ceil(m/8)] packed. */

@@ -42,6 +42,10 @@ class ldpc_params(C.Structure):
                 ("cn_rule", C.c_int32), ("offsets", C.c_void_p), ("offset_iters", C.c_int32)]
 
 
+class ldpc_schedule(C.Structure):
+    _fields_ = [("persistent_workgroups", C.c_int32), ("order", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -68,6 +72,18 @@ def lib():
         L.ldpc_code_plan.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ldpc_workspace_bytes.restype = C.c_size_t
         L.ldpc_workspace_bytes.argtypes = [vp, i32]
+        L.ldpc_decode_batch_sched.restype = C.c_int
+        L.ldpc_decode_batch_sched.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(ldpc_schedule), vp,
+                                              C.c_size_t, vp]
+        L.ldpc_workspace_bytes_sched.restype = C.c_size_t
+        L.ldpc_workspace_bytes_sched.argtypes = [vp, i32, C.POINTER(ldpc_schedule)]
+        L.ldpc_batch_create.restype = C.c_int
+        L.ldpc_batch_create.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(ldpc_schedule), vp, C.c_size_t,
+                                        C.POINTER(vp)]
+        L.ldpc_batch_launch.restype = C.c_int
+        L.ldpc_batch_launch.argtypes = [vp, vp]
+        L.ldpc_batch_destroy.restype = None
+        L.ldpc_batch_destroy.argtypes = [vp]
         L.ldpc_syndrome_batch.restype = C.c_int
         L.ldpc_syndrome_batch.argtypes = [vp, vp, i32, vp, vp]
         L.ldpc_last_error.restype = C.c_char_p
@@ -222,6 +238,76 @@ def ldpc_decode_batch(code: Code, syndromes, llr_in, n_frames: int, max_iter: in
     p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
     p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
     _check(lib().ldpc_decode_batch(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, _stream_ptr(stream)))
+
+
+def _schedule(n_frames: int, persistent_workgroups: int, order):
+    import torch
+    p_order = _dev_ptr(order, torch.int32, (n_frames,), "order")
+    return ldpc_schedule(int(persistent_workgroups), p_order)
+
+
+def ldpc_workspace_bytes_sched(code: Code, n_frames: int, persistent_workgroups: int = 0) -> int:
+    sch = ldpc_schedule(int(persistent_workgroups), None)
+    return int(lib().ldpc_workspace_bytes_sched(code.handle, int(n_frames), C.byref(sch)))
+
+
+def ldpc_decode_batch_sched(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
+                            out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, stream=None):
+    import torch
+    F = int(n_frames)
+    if F < 0:
+        raise ValueError("n_frames < 0")
+    if F == 0:
+        return
+    sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+    p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+    p_llr = _dev_ptr(llr_in, torch.int8, (F, code.n), "llr_in")
+    p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
+    p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
+    p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
+    sch = _schedule(F, persistent_workgroups, order)
+    need = int(lib().ldpc_workspace_bytes_sched(code.handle, F, C.byref(sch)))
+    p_ws, ws_bytes = None, 0
+    if workspace is not None:
+        p_ws = _dev_ptr(workspace, torch.uint8, (need,), "workspace")
+        ws_bytes = workspace.numel()
+    _check(lib().ldpc_decode_batch_sched(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, p_it,
+                                         C.byref(sch), p_ws, ws_bytes, _stream_ptr(stream)))
+
+
+class Batch:
+    """A decode of fixed device buffers captured as a HIP graph (ldpc_batch_*)."""
+
+    def __init__(self, code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
+                 out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None):
+        import torch
+        self._h = None
+        F = int(n_frames)
+        sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+        self._keep = (code, syndromes, llr_in, out_bits, out_converged, out_iters, order, workspace)
+        p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+        p_llr = _dev_ptr(llr_in, torch.int8, (F, code.n), "llr_in")
+        p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
+        p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
+        p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
+        sch = _schedule(F, persistent_workgroups, order)
+        need = int(lib().ldpc_workspace_bytes_sched(code.handle, F, C.byref(sch)))
+        p_ws, ws_bytes = None, 0
+        if workspace is not None:
+            p_ws = _dev_ptr(workspace, torch.uint8, (need,), "workspace")
+            ws_bytes = workspace.numel()
+        h = C.c_void_p()
+        _check(lib().ldpc_batch_create(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, p_it,
+                                       C.byref(sch), p_ws, ws_bytes, C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().ldpc_batch_launch(self._h, _stream_ptr(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ldpc_batch_destroy(self._h)
+            self._h = None
 
 
 def ldpc_syndrome_batch(code: Code, bits, n_frames: int, out_syn, stream=None):

@@ -8,6 +8,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -17,7 +18,7 @@ LIB = os.path.join(HERE, "libqkdldpc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qc_code.cpp", "capi.cpp", "decoder.hip"]
+SOURCES = ["qc_code.cpp", "capi.cpp", "syndrome.hip", "decode_scalar.hip", "decode_pairs.hip", "decode_split.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -40,15 +41,18 @@ def _run(cmd, verbose):
 
 def build(verbose: bool = False, resource_usage: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(OBJDIR, src + ".o")
         cmd = [HIPCC, *FLAGS, "-c", path, "-o", obj]
         if resource_usage and src.endswith(".hip"):
             cmd.append("-Rpass-analysis=kernel-resource-usage")
-        _run(cmd, verbose or resource_usage)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda j: _run(j[0], verbose or resource_usage), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)

@@ -168,7 +168,121 @@ int check_device(const ldpc_code *code)
     return LDPC_OK;
 }
 
+constexpr size_t kQueueBytes = 256;
+
+bool is_persistent(const ldpc_schedule *sched) { return sched && sched->persistent_workgroups > 0; }
+
+size_t workspace_need(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched)
+{
+    return (is_persistent(sched) ? kQueueBytes : 0) + code->ws_frame_bytes * (size_t)n_frames;
+}
+
+int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                      int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, const ldpc_schedule *sched)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: code is NULL");
+    if (n_frames < 0)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: n_frames < 0");
+    if (max_iter < 0)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: max_iter < 0");
+    if (n_frames > 0 && (!syndromes || !llr_in || !out_bits || !out_converged))
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: syndromes, llr_in, out_bits and out_converged must be non-NULL");
+    if (sched) {
+        if (sched->persistent_workgroups < 0)
+            return fail(LDPC_EINVAL, "ldpc_schedule: persistent_workgroups < 0");
+        if (sched->order && sched->persistent_workgroups == 0)
+            return fail(LDPC_EINVAL, "ldpc_schedule: order needs persistent_workgroups > 0");
+        if (sched->persistent_workgroups > 0 && !code->plan.split_dmax)
+            return fail(LDPC_EUNSUPPORTED, "ldpc_schedule: persistent workgroups need the split kernel family");
+    }
+    return LDPC_OK;
+}
+
+DecodeArgs make_args(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                     int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, int32_t *out_iters, int8_t *out_L,
+                     int16_t *out_E, const ldpc_schedule *sched, void *ws)
+{
+    DecodeArgs A{};
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    A.syn = syndromes;
+    A.llr = llr_in;
+    A.n_frames = n_frames;
+    A.max_iter = max_iter;
+    A.out_bits = out_bits;
+    A.out_conv = out_converged;
+    A.out_iters = out_iters;
+    A.out_L = out_L;
+    A.out_E = out_E;
+    if (is_persistent(sched)) {
+        A.persistent_wgs = sched->persistent_workgroups;
+        A.queue = reinterpret_cast<int *>(w);
+        A.order = sched->order;
+        w += kQueueBytes;
+    }
+    A.ws = code->ws_frame_bytes ? w : nullptr;
+    A.ws_frame_bytes = code->ws_frame_bytes;
+    A.ws_l_off = code->ws_l_off;
+    A.syn_bytes = (code->h.m + 7) / 8;
+    A.bit_bytes = (code->h.n + 7) / 8;
+    A.lds_e_off = code->lds_e_off;
+    A.lds_l_off = code->lds_l_off;
+    A.lds_syn_off = code->lds_syn_off;
+    A.lds_flag_off = code->lds_flag_off;
+    A.l_stride = code->l_stride;
+    A.lds_tab_off = code->lds_tab_off;
+    A.lane_tab = static_cast<const int4 *>(code->d_split);
+    A.blk2slot = code->d_split ? reinterpret_cast<const int32_t *>(static_cast<const uint8_t *>(code->d_split) +
+                                                                    code->lane_tab_bytes)
+                               : nullptr;
+    return A;
+}
+
+int decode_impl(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, int32_t *out_iters, int8_t *out_L,
+                int16_t *out_E, const ldpc_schedule *sched, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int rc = check_decode_args(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, sched);
+    if (rc != LDPC_OK || n_frames == 0)
+        return rc;
+    rc = check_device(code);
+    if (rc != LDPC_OK)
+        return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t need = workspace_need(code, n_frames, sched);
+    void *ws = workspace;
+    bool owned = false;
+    if (need > 0) {
+        if (ws && workspace_bytes < need)
+            return fail(LDPC_EINVAL, "ldpc_decode_batch: workspace smaller than the workspace size query");
+        if (!ws) {
+            hipError_t e = hipMallocAsync(&ws, need, s);
+            if (e != hipSuccess)
+                return hip_fail("ldpc_decode_batch: hipMallocAsync workspace", e);
+            owned = true;
+        }
+    }
+    const DecodeArgs A = make_args(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, out_iters,
+                                   out_L, out_E, sched, ws);
+    hipError_t e = qkdldpc::launch_decode(code->plan, code->dev, A, s);
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(ws, s);
+        if (e == hipSuccess)
+            e = e2;
+    }
+    if (e != hipSuccess)
+        return hip_fail("ldpc_decode_batch: kernel launch", e);
+    return LDPC_OK;
+}
+
 } // namespace
+
+struct ldpc_batch {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *owned_ws = nullptr;
+    int device = -1;
+};
 
 extern "C" {
 
@@ -315,67 +429,23 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
                          int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, int32_t *out_iters,
                          int8_t *out_L, int16_t *out_E, void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (!code)
-        return fail(LDPC_EINVAL, "ldpc_decode_batch: code is NULL");
-    if (n_frames < 0)
-        return fail(LDPC_EINVAL, "ldpc_decode_batch: n_frames < 0");
-    if (max_iter < 0)
-        return fail(LDPC_EINVAL, "ldpc_decode_batch: max_iter < 0");
-    if (n_frames == 0)
-        return LDPC_OK;
-    if (!syndromes || !llr_in || !out_bits || !out_converged)
-        return fail(LDPC_EINVAL, "ldpc_decode_batch: syndromes, llr_in, out_bits and out_converged must be non-NULL");
-    int rc = check_device(code);
-    if (rc != LDPC_OK)
-        return rc;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const size_t need = ldpc_workspace_bytes(code, n_frames);
-    void *ws = workspace;
-    bool owned = false;
-    if (need > 0) {
-        if (ws && workspace_bytes < need)
-            return fail(LDPC_EINVAL, "ldpc_decode_batch: workspace smaller than ldpc_workspace_bytes()");
-        if (!ws) {
-            hipError_t e = hipMallocAsync(&ws, need, s);
-            if (e != hipSuccess)
-                return hip_fail("ldpc_decode_batch: hipMallocAsync workspace", e);
-            owned = true;
-        }
-    }
-    DecodeArgs A{};
-    A.syn = syndromes;
-    A.llr = llr_in;
-    A.n_frames = n_frames;
-    A.max_iter = max_iter;
-    A.out_bits = out_bits;
-    A.out_conv = out_converged;
-    A.out_iters = out_iters;
-    A.out_L = out_L;
-    A.out_E = out_E;
-    A.ws = static_cast<uint8_t *>(ws);
-    A.ws_frame_bytes = code->ws_frame_bytes;
-    A.ws_l_off = code->ws_l_off;
-    A.syn_bytes = (code->h.m + 7) / 8;
-    A.bit_bytes = (code->h.n + 7) / 8;
-    A.lds_e_off = code->lds_e_off;
-    A.lds_l_off = code->lds_l_off;
-    A.lds_syn_off = code->lds_syn_off;
-    A.lds_flag_off = code->lds_flag_off;
-    A.l_stride = code->l_stride;
-    A.lds_tab_off = code->lds_tab_off;
-    A.lane_tab = static_cast<const int4 *>(code->d_split);
-    A.blk2slot = code->d_split ? reinterpret_cast<const int32_t *>(static_cast<const uint8_t *>(code->d_split) +
-                                                                    code->lane_tab_bytes)
-                               : nullptr;
-    hipError_t e = qkdldpc::launch_decode(code->plan, code->dev, A, s);
-    if (owned) {
-        hipError_t e2 = hipFreeAsync(ws, s);
-        if (e == hipSuccess)
-            e = e2;
-    }
-    if (e != hipSuccess)
-        return hip_fail("ldpc_decode_batch: kernel launch", e);
-    return LDPC_OK;
+    return decode_impl(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, out_iters, out_L, out_E,
+                       nullptr, workspace, workspace_bytes, stream);
+}
+
+int ldpc_decode_batch_sched(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                            int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, int32_t *out_iters,
+                            const ldpc_schedule *sched, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return decode_impl(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, out_iters, nullptr,
+                       nullptr, sched, workspace, workspace_bytes, stream);
+}
+
+size_t ldpc_workspace_bytes_sched(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched)
+{
+    if (!code || n_frames < 0)
+        return 0;
+    return workspace_need(code, n_frames, sched);
 }
 
 int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
@@ -383,6 +453,94 @@ int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int
 {
     return ldpc_decode_batch_ex(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, nullptr,
                                 nullptr, nullptr, nullptr, 0, stream);
+}
+
+int ldpc_batch_create(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                      int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged, int32_t *out_iters,
+                      const ldpc_schedule *sched, void *workspace, size_t workspace_bytes, ldpc_batch **out)
+{
+    if (!out)
+        return fail(LDPC_EINVAL, "ldpc_batch_create: out is NULL");
+    *out = nullptr;
+    int rc = check_decode_args(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, sched);
+    if (rc != LDPC_OK)
+        return rc;
+    if (n_frames == 0)
+        return fail(LDPC_EINVAL, "ldpc_batch_create: n_frames must be positive");
+    rc = check_device(code);
+    if (rc != LDPC_OK)
+        return rc;
+    ldpc_batch *b = new (std::nothrow) ldpc_batch;
+    if (!b)
+        return fail(LDPC_ENOMEM, "ldpc_batch_create: out of host memory");
+    b->device = code->device;
+    const size_t need = workspace_need(code, n_frames, sched);
+    void *ws = workspace;
+    hipError_t e = hipSuccess;
+    if (need > 0) {
+        if (ws && workspace_bytes < need) {
+            delete b;
+            return fail(LDPC_EINVAL, "ldpc_batch_create: workspace smaller than the workspace size query");
+        }
+        if (!ws) {
+            e = hipMalloc(&b->owned_ws, need);
+            if (e != hipSuccess) {
+                delete b;
+                return hip_fail("ldpc_batch_create: hipMalloc workspace", e);
+            }
+            ws = b->owned_ws;
+        }
+    }
+    const DecodeArgs A = make_args(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, out_iters,
+                                   nullptr, nullptr, sched, ws);
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = qkdldpc::launch_decode(code->plan, code->dev, A, cs);
+        hipError_t ec = hipStreamEndCapture(cs, &b->graph);
+        e = el != hipSuccess ? el : ec;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        ldpc_batch_destroy(b);
+        return hip_fail("ldpc_batch_create: graph capture", e);
+    }
+    *out = b;
+    return LDPC_OK;
+}
+
+int ldpc_batch_launch(ldpc_batch *batch, void *stream)
+{
+    if (!batch)
+        return fail(LDPC_EINVAL, "ldpc_batch_launch: batch is NULL");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess)
+        return hip_fail("hipGetDevice", e);
+    if (cur != batch->device)
+        return fail(LDPC_EINVAL, "ldpc_batch_launch: batch was created on another device");
+    e = hipGraphLaunch(batch->exec, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail("ldpc_batch_launch: hipGraphLaunch", e);
+    return LDPC_OK;
+}
+
+void ldpc_batch_destroy(ldpc_batch *batch)
+{
+    if (!batch)
+        return;
+    if (batch->exec)
+        (void)hipGraphExecDestroy(batch->exec);
+    if (batch->graph)
+        (void)hipGraphDestroy(batch->graph);
+    if (batch->owned_ws)
+        (void)hipFree(batch->owned_ws);
+    delete batch;
 }
 
 int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames, uint8_t *out_syn,

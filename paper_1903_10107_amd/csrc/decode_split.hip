@@ -1,0 +1,515 @@
+// gfx950 decode kernel, two lanes per row pair, 16-bit packed arithmetic,
+// state in LDS: the path of power-of-two Z with row degree up to 20.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace qkdldpc {
+
+// ---------------------------------------------------------------------------
+// Split variant: two adjacent lanes share a row pair, so a frame of Z = 1024
+// runs 16 waves per CU instead of 8. Both lanes execute the same code. Lane A
+// (even) holds edges 0 .. DH-1 of the row pair in order, lane B (odd) holds
+// edges DMAX-1 down to DH, so a left fold over a lane's own slots is the
+// forward partial F for A and the backward partial B for B. One lane swap
+// hands A the value B_DH and B the value F_{DH-1}; each lane then folds its
+// slots the other way, W_k, and its outputs are out_i = tau(X_{i-1}, W_{DH-1-i})
+// with out_0 = W_{DH-1}, which is the forward-backward fold edge by edge.
+//
+// Per-lane slot entries {c*Z | shift, LDS address of block column c, pad mask,
+// block} sit in LDS; padding slots point at a dummy block column past E, so
+// they need no store guards, and their operands are masked to 0 / kPad. E is
+// addressed with absolute LDS addresses (the table holds them), so no base is
+// added per access. L of a row pair is laid out [layer][half][slot][lane].
+//
+// When every row pair has its own lane pair (Z/2 <= threads/2), the syndrome
+// test of the state after iteration t-1 is folded into layer 0 of iteration t:
+// layer 0 reads exactly that state, so its rows' parities come from the
+// loaded values; only when all of them hold are the other layers tested,
+// before layer 0 writes anything.
+// ---------------------------------------------------------------------------
+
+typedef int8_t __attribute__((address_space(3))) lds_i8;
+typedef int16_t __attribute__((address_space(3))) lds_i16;
+template <typename ET>
+struct LdsPtr;
+template <>
+struct LdsPtr<int8_t> {
+    typedef lds_i8 *type;
+};
+template <>
+struct LdsPtr<int16_t> {
+    typedef lds_i16 *type;
+};
+
+// element at an absolute LDS byte address
+template <typename ET>
+__device__ __forceinline__ ET lds_ld(unsigned addr)
+{
+    return *(typename LdsPtr<ET>::type)(uintptr_t)addr;
+}
+template <typename ET>
+__device__ __forceinline__ void lds_st(unsigned addr, ET v)
+{
+    *(typename LdsPtr<ET>::type)(uintptr_t)addr = v;
+}
+
+// exchange a 32-bit value with the other lane of the pair (DPP quad_perm [1,0,3,2])
+__device__ __forceinline__ int swap_pair(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ s16x2 swap_pair(s16x2 x) { return __builtin_bit_cast(s16x2, swap_pair(__builtin_bit_cast(int, x))); }
+__device__ __forceinline__ u16x2 swap_pair(u16x2 x) { return __builtin_bit_cast(u16x2, swap_pair(__builtin_bit_cast(int, x))); }
+
+template <int DMIN, int DMAX>
+__host__ __device__ constexpr bool split_pad_slot(int i)
+{
+    // lane A's slot i is edge i; lane B's slot i is edge DMAX-1-i
+    return i >= DMIN || DMAX - 1 - i >= DMIN;
+}
+
+// Workgroup-wide OR of pred over three rotating LDS flag words: vote k writes
+// word k % 3, waits, reads it, and thread 0 clears word (k + 2) % 3, whose last
+// readers passed this barrier and whose next writers come after the next one.
+__device__ __forceinline__ int block_vote(int pred, int *flags, int &k)
+{
+    const int w = k;
+    if (pred)
+        flags[w] = 1;
+    __syncthreads();
+    const int any = flags[w];
+    if (threadIdx.x == 0)
+        flags[w == 0 ? 2 : w - 1] = 0;
+    k = w == 2 ? 0 : w + 1;
+    return any;
+}
+
+// E byte addresses of a row pair for its slot: a0 = ((r + shift) mod Z) + column
+// start, a1 = a0 with the Z/2 bit flipped (Z a power of two, column starts Z-aligned).
+__device__ __forceinline__ unsigned slot_addr(int4 te, int r, unsigned zm, unsigned esh)
+{
+    return ((((unsigned)r + (unsigned)te.x) & zm) << esh) | (unsigned)te.y;
+}
+
+template <int DH>
+struct SplitRow {
+    s16x2 e[DH], lk[DH];
+    unsigned a0[DH];
+    int pm[DH];
+};
+
+template <int DMIN, int DMAX, typename ET>
+__device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const int8_t *__restrict__ Lp,
+                                           const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+        const int4 te = tab[2 * i];
+        const unsigned a0 = slot_addr(te, r, zm, esh);
+        R.a0[i] = a0;
+        R.pm[i] = te.z;
+        s16x2 ev;
+        ev.x = (short)lds_ld<ET>(a0);
+        ev.y = (short)lds_ld<ET>(a0 ^ hzb);
+        R.e[i] = ev;
+        s16x2 lv;
+        lv.x = (short)Lp[2 * i];
+        lv.y = (short)Lp[2 * DH + 2 * i];
+        R.lk[i] = lv;
+    }
+}
+
+// XOR of the hard-decision sign bits of the row pair's slots held by this lane
+template <int DMIN, int DMAX>
+__device__ __forceinline__ s16x2 split_e_parity(const SplitRow<DMAX / 2> &R)
+{
+    constexpr int DH = DMAX / 2;
+    s16x2 own = splat2(0);
+#pragma unroll
+    for (int i = 0; i < DH; ++i)
+        own ^= split_pad_slot<DMIN, DMAX>(i) ? (R.e[i] & __builtin_bit_cast(s16x2, R.pm[i])) : R.e[i];
+    return own;
+}
+
+template <int DMIN, int DMAX, typename ET, int RULE>
+__device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DMAX / 2> &R, int8_t *__restrict__ Lp,
+                                             s16x2 syn, unsigned hzb)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr int ACC = AccLim<ET>::value;
+    const s16x2 em = splat2(C.e_max);
+    const u16x2 mm = usplat2(C.msg_max);
+    s16x2 v[DH];
+    u16x2 p[DH], X[DH], W[DH];
+    s16x2 own = splat2(0);
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+        // Eq. 8, saturated to the soft-value range
+        s16x2 vi = vmin2(vmax2(__builtin_elementwise_sub_sat(R.e[i], R.lk[i]), splat2(-ACC)), splat2(ACC));
+        u16x2 pi = as_u(vmin2(vmax2(vi, -vi), as_s(mm)));
+        if (split_pad_slot<DMIN, DMAX>(i)) {
+            const u16x2 mk = __builtin_bit_cast(u16x2, R.pm[i]);
+            vi = vi & __builtin_bit_cast(s16x2, R.pm[i]);
+            pi = (pi & mk) | (usplat2(kPad) & ~mk);
+        }
+        v[i] = vi;
+        own ^= vi;
+        p[i] = pi;
+    }
+    // sign product of Eq. 1 over the whole row, times the syndrome bit
+    const s16x2 par = syn ^ own ^ swap_pair(own);
+    u16x2 out[DH];
+    if constexpr (RULE == kRuleMinSum) {
+        u16x2 m1 = usplat2(0x7fff), m2 = usplat2(0x7fff);
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            m2 = umin2(m2, umax2(m1, p[i]));
+            m1 = umin2(m1, p[i]);
+        }
+        const u16x2 o1 = swap_pair(m1), o2 = swap_pair(m2);
+        m2 = umin2(umin2(m2, o2), umax2(m1, o1));
+        m1 = umin2(m1, o1);
+        const u16x2 diff = m2 - m1;
+#pragma unroll
+        for (int i = 0; i < DH; ++i)
+            out[i] = m2 - umin2(p[i] - m1, usplat2(1)) * diff;
+    } else {
+        X[0] = p[0];
+#pragma unroll
+        for (int i = 1; i < DH; ++i)
+            X[i] = tau2(X[i - 1], p[i]);
+        W[0] = swap_pair(X[DH - 1]);
+#pragma unroll
+        for (int k = 1; k < DH; ++k)
+            W[k] = tau2(W[k - 1], p[DH - k]);
+        out[0] = W[DH - 1];
+#pragma unroll
+        for (int i = 1; i < DH; ++i)
+            out[i] = tau2(X[i - 1], W[DH - 1 - i]);
+    }
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+        const s16x2 sg = (par ^ v[i]) >> (short)15;  // -1 in a half whose message is negative
+        const s16x2 mg = as_s(out[i]);
+        const s16x2 ln = (mg ^ sg) - sg;
+        // Eq. 9 under Alg. 2: halves whose stored |E| is E_max keep E
+        const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln), -em), em);
+        const s16x2 ae = vmax2(R.e[i], -R.e[i]);
+        const s16x2 frozen = vmin2(em - ae, splat2(1)) - splat2(1);
+        const s16x2 o = (frozen & R.e[i]) | (~frozen & ne);
+        lds_st<ET>(R.a0[i], (ET)o.x);
+        lds_st<ET>(R.a0[i] ^ hzb, (ET)o.y);
+        Lp[2 * i] = (int8_t)ln.x;
+        Lp[2 * DH + 2 * i] = (int8_t)ln.y;
+    }
+}
+
+// 1 when some check row of layers [b0, b1) owned by this lane pair fails
+template <int DMIN, int DMAX, typename ET>
+__device__ __forceinline__ int split_rows_unsat(const DevCode &C, const uint8_t *__restrict__ s_syn,
+                                                const int4 *__restrict__ s_tab, int h, int r, int b0, int b1)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+    const int z = C.z, hz = z >> 1;
+    const unsigned zm = (unsigned)(z - 1), hzb = (unsigned)hz << esh;
+    s16x2 any = splat2(0);
+    for (int b = b0; b < b1; ++b) {
+        const int4 *tab = s_tab + b * DH * 2 + h;
+        s16x2 x[DH];
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            const int4 te = tab[2 * i];
+            const unsigned a0 = slot_addr(te, r, zm, esh);
+            x[i].x = (short)lds_ld<ET>(a0);
+            x[i].y = (short)lds_ld<ET>(a0 ^ hzb);
+            if (split_pad_slot<DMIN, DMAX>(i))
+                x[i] = x[i] & __builtin_bit_cast(s16x2, te.z);
+        }
+        s16x2 own = splat2(0);
+#pragma unroll
+        for (int i = 0; i < DH; ++i)
+            own ^= x[i];
+        any |= syn_pair(s_syn, b * z + r, b * z + r + hz) ^ own ^ swap_pair(own);
+    }
+    return (any.x | any.y) < 0;
+}
+
+// LDS regions of the split kernel, set up once per workgroup.
+template <typename ET>
+struct SplitLds {
+    ET *E;          // E plus one dummy block column, at offset 0
+    int8_t *L;      // [row pair][layer][half][slot][lane]
+    uint8_t *syn;   // packed syndrome of the current frame
+    int4 *tab;      // per-lane slot table with absolute column addresses
+    int *flags;     // three vote words and one queue slot
+};
+
+// Decode frame f with one workgroup (the LDS table must already be staged).
+template <int DMIN, int DMAX, typename ET, int RULE>
+__device__ __forceinline__ void split_decode_frame(const DevCode &C, const DecodeArgs &A, const SplitLds<ET> &M, int f)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int z = C.z, n = C.n, hz = z >> 1, h = tid & 1;
+    const unsigned zm = (unsigned)(z - 1), hzb = (unsigned)hz << esh;
+    ET *E = M.E;
+    int8_t *L = M.L;
+    uint8_t *s_syn = M.syn;
+    const int4 *s_tab = M.tab;
+    int *flags = M.flags;
+    const int S = A.l_stride;
+
+    // stage in: syndrome, E, L = 0, vote words
+    const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
+    for (int i = tid; i < A.syn_bytes; i += nthr)
+        s_syn[i] = syn[i];
+    stage_llr<ET>(E, A.llr + (size_t)f * n, n, C.e_max < 127 ? C.e_max : 127, tid, nthr);
+    uint4 *L128 = reinterpret_cast<uint4 *>(L);
+    for (int w = tid; w < (hz * S) >> 4; w += nthr)
+        L128[w] = uint4{0, 0, 0, 0};
+    for (int w = ((hz * S) & ~15) + tid; w < hz * S; w += nthr)
+        L[w] = 0;
+    if (tid < 3)
+        flags[tid] = 0;
+    __syncthreads();
+    int vk = 0;
+    int conv, iters = 0;
+    if (hz <= (nthr >> 1)) {
+        // one row pair per lane pair: the check is folded into layer 0
+        const int r = tid >> 1;
+        const bool act = r < hz;
+        int8_t *Lr = L + r * S + h;
+        conv = !block_vote(act ? split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 0, C.mb) : 0, flags, vk);
+        for (int t = 1; t <= A.max_iter && !conv; ++t) {
+            {
+                SplitRow<DH> R;
+                const s16x2 syn0 = act ? syn_pair(s_syn, r, r + hz) : splat2(0);
+                if (act)
+                    split_load<DMIN, DMAX, ET>(R, Lr, s_tab + h, r, zm, hzb);
+                if (t >= 2) {
+                    int fail0 = 0;
+                    if (act) {
+                        const s16x2 own = split_e_parity<DMIN, DMAX>(R);
+                        const s16x2 pe = syn0 ^ own ^ swap_pair(own);
+                        fail0 = (pe.x | pe.y) < 0;
+                    }
+                    if (!block_vote(fail0, flags, vk)) {
+                        const int failr = act ? split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 1, C.mb) : 0;
+                        if (!block_vote(failr, flags, vk)) {
+                            conv = 1;
+                            iters = t - 1;
+                            break;
+                        }
+                    }
+                }
+                if (act)
+                    split_finish<DMIN, DMAX, ET, RULE>(C, R, Lr, syn0, hzb);
+                __syncthreads();
+            }
+            for (int b = 1; b < C.mb; ++b) {
+                if (act) {
+                    SplitRow<DH> R;
+                    int8_t *Lb = Lr + b * 4 * DH;
+                    split_load<DMIN, DMAX, ET>(R, Lb, s_tab + b * DH * 2 + h, r, zm, hzb);
+                    split_finish<DMIN, DMAX, ET, RULE>(C, R, Lb, syn_pair(s_syn, b * z + r, b * z + r + hz), hzb);
+                }
+                __syncthreads();
+            }
+            iters = t;
+        }
+        if (!conv && A.max_iter > 0)
+            conv = !block_vote(act ? split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 0, C.mb) : 0, flags,
+                               vk);
+    } else {
+        // several row pairs per lane pair: separate check after every iteration
+        auto unsat_all = [&]() {
+            int u = 0;
+            for (int r = tid >> 1; r < hz; r += nthr >> 1)
+                u |= split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 0, C.mb);
+            return u;
+        };
+        conv = !block_vote(unsat_all(), flags, vk);
+        for (int t = 1; t <= A.max_iter && !conv; ++t) {
+            for (int b = 0; b < C.mb; ++b) {
+                for (int r = tid >> 1; r < hz; r += nthr >> 1) {
+                    SplitRow<DH> R;
+                    int8_t *Lb = L + r * S + h + b * 4 * DH;
+                    split_load<DMIN, DMAX, ET>(R, Lb, s_tab + b * DH * 2 + h, r, zm, hzb);
+                    split_finish<DMIN, DMAX, ET, RULE>(C, R, Lb, syn_pair(s_syn, b * z + r, b * z + r + hz), hzb);
+                }
+                __syncthreads();
+            }
+            iters = t;
+            conv = !block_vote(unsat_all(), flags, vk);
+        }
+    }
+    if (!conv)
+        iters = A.max_iter;
+
+    // stage out: hard decisions (wavefront ballot), flags, optional state
+    const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    const int nwords = (n + 63) >> 6;
+    uint8_t *ob = A.out_bits + (size_t)f * A.bit_bytes;
+    for (int w = wv; w < nwords; w += nwv) {
+        const int j = (w << 6) + lane;
+        const bool neg = j < n && E[j] < 0;
+        const unsigned long long mask = __ballot(neg);
+        if (lane < 8) {
+            const int byte = (w << 3) + lane;
+            if (byte < A.bit_bytes)
+                ob[byte] = (uint8_t)(mask >> (8 * lane));
+        }
+    }
+    if (tid == 0) {
+        A.out_conv[f] = (uint8_t)conv;
+        if (A.out_iters)
+            A.out_iters[f] = iters;
+    }
+    if (A.out_L) {
+        // canonical [block][row] layout
+        const int ne = C.n_blocks * z;
+        for (int e = tid; e < ne; e += nthr) {
+            const int blk = e / z, row = e - blk * z;
+            const int half = row >= hz, r = row - half * hz;
+            A.out_L[(size_t)f * ne + e] = L[r * S + A.blk2slot[blk] + half * 2 * DH];
+        }
+    }
+    if (A.out_E)
+        for (int j = tid; j < n; j += nthr)
+            A.out_E[(size_t)f * n + j] = (int16_t)E[j];
+}
+
+// Split LDS layout and the ebase invariant: the slot addresses OR a column
+// start into a row offset, which needs E to start at a multiple of Z elements;
+// these kernels use no static LDS, so the dynamic area starts at 0.
+template <typename ET>
+__device__ __forceinline__ bool split_setup(const DevCode &C, const DecodeArgs &A, SplitLds<ET> &M)
+{
+    constexpr int DH_UNUSED = 0;
+    (void)DH_UNUSED;
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+    extern __shared__ __align__(16) uint8_t smem[];
+    M.E = reinterpret_cast<ET *>(smem);
+    M.L = reinterpret_cast<int8_t *>(smem + A.lds_l_off);
+    M.syn = smem + A.lds_syn_off;
+    M.tab = reinterpret_cast<int4 *>(smem + A.lds_tab_off);
+    M.flags = reinterpret_cast<int *>(smem + A.lds_flag_off);
+    const unsigned ebase = (unsigned)(uintptr_t)M.E;
+    return (ebase & ((unsigned)(C.z << esh) - 1)) == 0;
+}
+
+template <typename ET>
+__device__ __forceinline__ void split_stage_table(const DevCode &C, const DecodeArgs &A, const SplitLds<ET> &M,
+                                                  int dh)
+{
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+    const unsigned ebase = (unsigned)(uintptr_t)M.E;
+    for (int q = threadIdx.x; q < C.mb * dh * 2; q += blockDim.x) {
+        int4 te = A.lane_tab[q];
+        te.y = (int)(((unsigned)te.y << esh) + ebase);
+        M.tab[q] = te;
+    }
+}
+
+// One workgroup per frame (grid = frames).
+template <int DMIN, int DMAX, typename ET, int RULE>
+__global__ __launch_bounds__(1024) void k_decode_frame_split(DevCode C, DecodeArgs A)
+{
+    SplitLds<ET> M;
+    const int f = blockIdx.x;
+    if (!split_setup<ET>(C, A, M)) {
+        if (threadIdx.x == 0) {
+            A.out_conv[f] = 0;
+            if (A.out_iters)
+                A.out_iters[f] = -1;
+        }
+        return;
+    }
+    split_stage_table<ET>(C, A, M, DMAX / 2);
+    split_decode_frame<DMIN, DMAX, ET, RULE>(C, A, M, f);
+}
+
+// Persistent workgroups: each one takes the next position of a device queue
+// (atomic counter, reset to 0 by k_queue_reset before the launch), decodes
+// frame order[position] (or position), and stops once the queue is past the
+// last frame, which every wave of every workgroup reaches.
+template <int DMIN, int DMAX, typename ET, int RULE>
+__global__ __launch_bounds__(1024) void k_decode_split_persistent(DevCode C, DecodeArgs A)
+{
+    SplitLds<ET> M;
+    if (!split_setup<ET>(C, A, M))
+        return;
+    split_stage_table<ET>(C, A, M, DMAX / 2);
+    for (;;) {
+        __syncthreads();  // the previous frame's stage-out is done with E and the queue slot
+        if (threadIdx.x == 0)
+            M.flags[3] = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int q = M.flags[3];
+        if (q >= A.n_frames)
+            break;
+        const int f = A.order ? A.order[q] : q;
+        if ((unsigned)f < (unsigned)A.n_frames)
+            split_decode_frame<DMIN, DMAX, ET, RULE>(C, A, M, f);
+    }
+}
+
+namespace {
+
+template <int DMIN, int DMAX, typename ET, int RULE>
+hipError_t launch_one_split(const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
+{
+    const bool persistent = A.persistent_wgs > 0;
+    auto kern = persistent ? k_decode_split_persistent<DMIN, DMAX, ET, RULE> : k_decode_frame_split<DMIN, DMAX, ET, RULE>;
+    if (lds > 65536) {
+        hipError_t e = persistent ? allow_max_lds<k_decode_split_persistent<DMIN, DMAX, ET, RULE>>()
+                                  : allow_max_lds<k_decode_frame_split<DMIN, DMAX, ET, RULE>>();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (persistent) {
+        hipError_t e = launch_queue_reset(A.queue, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(persistent ? A.persistent_wgs : A.n_frames), dim3(threads), lds, s, C, A);
+    return hipGetLastError();
+}
+
+template <int DMIN, int DMAX, typename ET>
+hipError_t launch_rule_split(int rule, const DevCode &C, const DecodeArgs &A, int threads, size_t lds,
+                             hipStream_t s)
+{
+    if (rule == LDPC_RULE_MINSUM)
+        return launch_one_split<DMIN, DMAX, ET, kRuleMinSum>(C, A, threads, lds, s);
+    return launch_one_split<DMIN, DMAX, ET, kRuleRcbpFB>(C, A, threads, lds, s);
+}
+
+template <typename ET>
+hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+{
+    switch (P.split_dmax) {
+    case 8:
+        return P.min_deg >= 6 ? launch_rule_split<6, 8, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
+                              : launch_rule_split<2, 8, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+    default:
+        return P.min_deg >= 19 ? launch_rule_split<19, 20, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
+                               : launch_rule_split<2, 20, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+    }
+}
+
+} // namespace
+
+hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+{
+    return P.acc_bits == 16 ? launch_split<int16_t>(P, C, A, s) : launch_split<int8_t>(P, C, A, s);
+}
+
+} // namespace qkdldpc

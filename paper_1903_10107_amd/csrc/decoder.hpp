@@ -29,6 +29,9 @@ struct DecodeArgs {
     int lds_tab_off;      // split kernel: per-lane slot table in LDS
     const int4 *lane_tab; // split kernel: [mb][DMAX/2][2] {c*Z | shift, c*Z, pad mask, block}
     const int32_t *blk2slot; // split kernel: block -> byte offset of its slot in a row pair's L slice
+    int persistent_wgs;   // > 0: that many persistent workgroups pull frames from a queue
+    int *queue;           // persistent: device counter (reset by k_queue_reset)
+    const int32_t *order; // persistent: decode order, a permutation of the frames, or nullptr
 };
 
 struct LaunchPlan {
@@ -44,6 +47,10 @@ struct LaunchPlan {
 };
 
 hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+hipError_t launch_decode_scalar(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s);
+hipError_t launch_queue_reset(int *queue, hipStream_t s);
 
 } // namespace qkdldpc

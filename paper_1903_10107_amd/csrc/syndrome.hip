@@ -1,0 +1,68 @@
+// Alice's side of the syndrome exchange (s = H x) and small utility kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace qkdldpc {
+
+// Alice's side: s = H x for packed x, one thread per check row, packed with a ballot.
+__global__ __launch_bounds__(256) void k_syndrome(DevCode C, const uint8_t *__restrict__ bits, int bit_bytes,
+                                                  uint8_t *__restrict__ out_syn, int syn_bytes)
+{
+    const int f = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int par = 0;
+    if (i < C.m) {
+        const int b = i / C.z, r = i - b * C.z;
+        const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
+        const uint8_t *x = bits + (size_t)f * bit_bytes;
+        for (int k = 0; k < d; ++k) {
+            const int j = ldc(C.colbase, o + k) + rot(r, ldc(C.shift, o + k), C.z);
+            par ^= (x[j >> 3] >> (j & 7)) & 1;
+        }
+    }
+    const unsigned long long mask = __ballot(par);
+    const int lane = threadIdx.x & 63;
+    const int w0 = i - lane;  // first row of this wave, a multiple of 64
+    if (lane < 8) {
+        const int byte = (w0 >> 3) + lane;
+        if (byte < syn_bytes)
+            out_syn[(size_t)f * syn_bytes + byte] = (uint8_t)(mask >> (8 * lane));
+    }
+}
+
+hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s)
+{
+    const int bit_bytes = (C.n + 7) / 8, syn_bytes = (C.m + 7) / 8;
+    const int threads = 256;
+    dim3 grid((C.m + threads - 1) / threads, n_frames);
+    hipLaunchKernelGGL(k_syndrome, grid, dim3(threads), 0, s, C, bits, bit_bytes, out_syn, syn_bytes);
+    return hipGetLastError();
+}
+
+// Reset the frame queue of a persistent launch (a kernel, not a memset, so that
+// the pair can be captured in a graph and replayed).
+__global__ void k_queue_reset(int *queue)
+{
+    if (threadIdx.x == 0)
+        *queue = 0;
+}
+
+hipError_t launch_queue_reset(int *queue, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+{
+    if (P.split_dmax)
+        return launch_decode_split(P, C, A, s);
+    if (P.pairs)
+        return launch_decode_pairs(P, C, A, s);
+    return launch_decode_scalar(P, C, A, s);
+}
+
+} // namespace qkdldpc

@@ -111,6 +111,21 @@ def test_cases_cover_every_kernel_family(B):
     assert seen == {"global", "lds", "pairs", "split"}, seen
 
 
+def test_llr_minus_128_is_read_as_minus_127(B):
+    """-128 anywhere in a row (the vectorized stage-in fixes it byte by byte)."""
+    code = I.Code(I.make_base(5, 32, 1024), 1024)
+    fr = I.make_frames(code, 4, 0.02, 77, n_short=int(0.33 * code.n))
+    llr = fr.llr.copy()
+    rng = np.random.default_rng(5)
+    llr[rng.random(llr.shape) < 0.05] = -128
+    llr[:, 1:9] = np.array([-128, -127, -128, 1, -128, 0, -128, -128], dtype=np.int8)
+    gc = B.Code(code.base, code.z)
+    _say(f"[gpu parity] llr -128: {gc.plan()}")
+    got = B.decode(gc, fr.syn, llr, 30, want_state=True)
+    ref = O.decode(code.base, code.z, fr.syn, llr, 30, want_state=True)
+    _compare(got, ref)
+
+
 def test_n_frames_zero_is_a_noop(B):
     import torch
     code = B.Code(I.make_base(5, 32, 32), 32)

@@ -1,0 +1,122 @@
+"""Batch schedules and graph-captured batches: the decoded results do not depend
+on the schedule. Persistent workgroups with and without a decode order, and a
+graph replayed several times with eager work and synchronizations between the
+replays, are compared with the one-workgroup-per-frame decode and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_10107_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1903_10107_amd import binding
+    binding.lib()
+    return binding
+
+
+def _setup(B, z=1024, F=40, q=0.02, short=0.30, seed=31):
+    import torch
+    code = I.Code(I.make_base(5, 32, z), z)
+    fr = I.make_frames(code, F, q, seed, n_short=int(short * code.n))
+    gc = B.Code(code.base, code.z)
+    dev = dict(syn=torch.from_numpy(fr.syn).cuda(), llr=torch.from_numpy(fr.llr).cuda())
+    return code, fr, gc, dev
+
+
+def _outs(code, F):
+    import torch
+    return (torch.zeros((F, (code.n + 7) // 8), dtype=torch.uint8, device="cuda"),
+            torch.zeros(F, dtype=torch.uint8, device="cuda"),
+            torch.zeros(F, dtype=torch.int32, device="cuda"))
+
+
+@pytest.mark.parametrize("wgs,ordered", [(1, False), (7, True), (64, False), (300, True)])
+def test_persistent_schedule_matches_oracle(B, wgs, ordered):
+    import torch
+    code, fr, gc, dev = _setup(B)
+    F = fr.n_frames
+    _say(f"[gpu schedule] persistent wgs={wgs} ordered={ordered} {gc.plan()}")
+    order = None
+    if ordered:
+        order = torch.from_numpy(np.random.default_rng(wgs).permutation(F).astype(np.int32)).cuda()
+    bits, conv, iters = _outs(code, F)
+    B.ldpc_decode_batch_sched(gc, dev["syn"], dev["llr"], F, 50, bits, conv, iters, persistent_workgroups=wgs,
+                              order=order)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, 50)
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+    assert np.array_equal(conv.cpu().numpy(), ref["conv"])
+    assert np.array_equal(iters.cpu().numpy(), ref["iters"])
+
+
+def test_order_with_out_of_range_entries_skips_them(B):
+    import torch
+    code, fr, gc, dev = _setup(B, F=12)
+    F = fr.n_frames
+    order = torch.tensor([3, 99, -1, 5] + list(range(6, 12)) + [0, 1], dtype=torch.int32, device="cuda")
+    bits, conv, iters = _outs(code, F)
+    iters.fill_(-7)
+    B.ldpc_decode_batch_sched(gc, dev["syn"], dev["llr"], F, 50, bits, conv, iters, persistent_workgroups=3,
+                              order=order)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, 50)
+    it = iters.cpu().numpy()
+    done = [0, 1, 3, 5] + list(range(6, 12))
+    assert np.array_equal(it[done], ref["iters"][done])
+    assert it[2] == -7 and it[4] == -7
+
+
+def test_schedule_argument_errors(B):
+    import torch
+    code, fr, gc, dev = _setup(B, F=4)
+    bits, conv, iters = _outs(code, 4)
+    order = torch.arange(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(B.LdpcError):
+        B.ldpc_decode_batch_sched(gc, dev["syn"], dev["llr"], 4, 10, bits, conv, iters, persistent_workgroups=0,
+                                  order=order)
+    odd = B.Code(I.make_base(4, 12, 37, 3, 5), 37)          # odd Z: not the split family
+    fr2 = I.make_frames(I.Code(odd.base, 37), 2, 0.02, 1)
+    b2, c2, i2 = _outs(I.Code(odd.base, 37), 2)
+    with pytest.raises(B.LdpcError) as ei:
+        B.ldpc_decode_batch_sched(odd, torch.from_numpy(fr2.syn).cuda(), torch.from_numpy(fr2.llr).cuda(), 2, 10,
+                                  b2, c2, i2, persistent_workgroups=4)
+    assert ei.value.code == B.LDPC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("wgs", [0, 256])
+def test_graph_batch_replays_match_eager(B, wgs):
+    import torch
+    code, fr, gc, dev = _setup(B, F=64, seed=41)
+    F = fr.n_frames
+    _say(f"[gpu graph] wgs={wgs}")
+    eb, ec, ei = _outs(code, F)
+    B.ldpc_decode_batch_sched(gc, dev["syn"], dev["llr"], F, 50, eb, ec, ei, persistent_workgroups=wgs)
+    torch.cuda.synchronize()
+    eager = (eb.cpu().numpy(), ec.cpu().numpy(), ei.cpu().numpy())
+    gb, gcv, gi = _outs(code, F)
+    batch = B.Batch(gc, dev["syn"], dev["llr"], F, 50, gb, gcv, gi, persistent_workgroups=wgs)
+    for rep in range(4):
+        gb.zero_()
+        gcv.zero_()
+        gi.fill_(-1)
+        scratch = torch.randn(1 << 16, device="cuda").sum()    # eager work between replays
+        batch.launch()
+        torch.cuda.synchronize()
+        assert float(scratch) == float(scratch)
+        assert np.array_equal(gb.cpu().numpy(), eager[0]), rep
+        assert np.array_equal(gcv.cpu().numpy(), eager[1]), rep
+        assert np.array_equal(gi.cpu().numpy(), eager[2]), rep
+    del batch
