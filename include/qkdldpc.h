@@ -69,7 +69,12 @@ typedef struct {
                                row min(t-1, offset_iters-1), result clamped to [0, msg_max];
                                copied at create. NULL = no offsets (the paper's decoder). */
     int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
+    int32_t kernel_hint;    /* 0: pick the kernel family automatically; LDPC_HINT_*: use that
+                               family, or fail with LDPC_EUNSUPPORTED when it does not apply
+                               (for tuning and testing; results do not depend on it) */
 } ldpc_params;
+
+enum { LDPC_HINT_AUTO = 0, LDPC_HINT_GLOBAL = 1, LDPC_HINT_LDS = 2, LDPC_HINT_PAIRS = 3, LDPC_HINT_SPLIT = 4 };
 
 /* Build a code from a quasi-cyclic base matrix (Sec. 4.1).
  * base: HOST, int32 [mb][nb] row-major; -1 = zero block, 0..z-1 = circulant shift.

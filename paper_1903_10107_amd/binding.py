@@ -29,6 +29,7 @@ LDPC_RULE_RCBP_EQ7 = 1
 LDPC_RULE_MINSUM = 2
 
 KERNEL_NAMES = {0: "global", 1: "lds", 2: "pairs", 3: "split"}
+KERNEL_HINTS = {"auto": 0, "global": 1, "lds": 2, "pairs": 3, "split": 4}
 
 
 class LdpcError(RuntimeError):
@@ -39,7 +40,8 @@ class LdpcError(RuntimeError):
 
 class ldpc_params(C.Structure):
     _fields_ = [("msg_max", C.c_int32), ("e_max", C.c_int32), ("acc_bits", C.c_int32),
-                ("cn_rule", C.c_int32), ("offsets", C.c_void_p), ("offset_iters", C.c_int32)]
+                ("cn_rule", C.c_int32), ("offsets", C.c_void_p), ("offset_iters", C.c_int32),
+                ("kernel_hint", C.c_int32)]
 
 
 class ldpc_schedule(C.Structure):
@@ -128,7 +130,7 @@ class Code:
     """A QC-LDPC code handle (ldpc_code_create / ldpc_code_destroy)."""
 
     def __init__(self, base, z: int, *, msg_max: int = 0, e_max: int = 0, acc_bits: int = 0,
-                 cn_rule: int = LDPC_RULE_RCBP_FB, offsets=None):
+                 cn_rule: int = LDPC_RULE_RCBP_FB, offsets=None, kernel: str = "auto"):
         self._h = None
         base = np.ascontiguousarray(base, dtype=np.int32)
         if base.ndim != 2:
@@ -136,7 +138,7 @@ class Code:
         self.base = base
         self.z = int(z)
         self._offsets = None
-        prm = ldpc_params(msg_max, e_max, acc_bits, cn_rule, None, 0)
+        prm = ldpc_params(msg_max, e_max, acc_bits, cn_rule, None, 0, KERNEL_HINTS[kernel])
         if offsets is not None:
             self._offsets = np.ascontiguousarray(offsets, dtype=np.int8)
             if self._offsets.ndim != 2 or self._offsets.shape[1] != int((base >= 0).sum()):

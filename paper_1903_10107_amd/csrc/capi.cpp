@@ -78,7 +78,9 @@ std::vector<int32_t> split_tables(const HostCode &h, int dmax)
     return t;
 }
 
-void make_plan(ldpc_code *c, int lds_limit)
+// Kernel families in order of preference; each applies under its own conditions.
+// Returns false when the requested family (hint > 0) does not apply.
+bool make_plan(ldpc_code *c, int lds_limit, int hint)
 {
     const HostCode &h = c->h;
     const size_t esize = h.acc_bits == 16 ? 2 : 1;
@@ -87,30 +89,24 @@ void make_plan(ldpc_code *c, int lds_limit)
     P.cn_rule = h.cn_rule;
     P.min_deg = h.min_deg;
     P.max_deg = h.max_deg;
-    P.threads = (int)std::min<size_t>(1024, round_up((size_t)h.z, 64));
-    // Scalar kernel LDS layout: E at offset 0, L [block][row], the syndrome.
-    const size_t syn_bytes = (size_t)(h.m + 7) / 8;
-    const size_t e_al = round_up((size_t)h.n * esize, 16);
-    const size_t l_al = round_up((size_t)h.n_edges, 16);
-    const size_t total = e_al + l_al + syn_bytes;
-    c->lds_e_off = 0;
-    c->lds_l_off = (int)e_al;
-    c->lds_syn_off = (int)(e_al + l_al);
     P.pow2 = (h.z & (h.z - 1)) == 0;
     P.pairs = false;
     P.split_dmax = 0;
-    // Split kernel (two lanes per row pair): power-of-two Z, forward-backward or
-    // min-sum rule, no offsets, row degree <= 20. LDS: E plus a dummy block
-    // column, L as [pair][layer][half][slot][lane] with an odd-dword pair stride,
-    // the syndrome, the lane table, two flag words.
-    if (P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
+    const size_t syn_bytes = (size_t)(h.m + 7) / 8;
+    const size_t e_al = round_up((size_t)h.n * esize, 16);
+
+    // Split (two lanes per row pair): power-of-two Z, forward-backward or min-sum
+    // rule, no offsets, row degree <= 20. LDS: E plus a dummy block column, L as
+    // [pair][layer][half][slot][lane] with an odd-dword pair stride, the
+    // syndrome, the lane table, three vote words and the queue slot.
+    if ((hint == 0 || hint == LDPC_HINT_SPLIT) && P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
         (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM)) {
         const int dmax = h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
         const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
         const size_t stride = (((size_t)h.mb * dh) | 1) * 4;
         const size_t l_sp = round_up((size_t)(h.z / 2) * stride, 16);
         const size_t tab = (size_t)h.mb * dh * 2 * 16;
-        const size_t total_sp = e_sp + l_sp + round_up(syn_bytes, 16) + tab + 16;  // three vote words
+        const size_t total_sp = e_sp + l_sp + round_up(syn_bytes, 16) + tab + 16;
         if (total_sp <= (size_t)lds_limit) {
             P.split_dmax = dmax;
             P.lds_state = true;
@@ -123,15 +119,18 @@ void make_plan(ldpc_code *c, int lds_limit)
             c->lds_flag_off = (int)(c->lds_tab_off + tab);
             c->ws_frame_bytes = 0;
             c->lane_tab_bytes = tab;
-            return;
+            return true;
         }
     }
-    // Packed kernel LDS layout: E at offset 0, L as [pair][block][half] with an
-    // odd-dword stride per pair, the syndrome, two flag words.
+    if (hint == LDPC_HINT_SPLIT)
+        return false;
+    // Pairs (one lane per row pair): even Z. LDS: E at offset 0, L as
+    // [pair][block][half] with an odd-dword stride per pair, the syndrome, two
+    // vote words.
     const size_t stride = (((2 * (size_t)h.n_blocks + 3) / 4) | 1) * 4;
     const size_t lp_al = round_up((size_t)(h.z / 2) * stride, 16);
     const size_t total_x2 = e_al + lp_al + round_up(syn_bytes, 16) + 16;
-    if (h.z % 2 == 0 && total_x2 <= (size_t)lds_limit) {
+    if ((hint == 0 || hint == LDPC_HINT_PAIRS) && h.z % 2 == 0 && total_x2 <= (size_t)lds_limit) {
         P.pairs = true;
         P.lds_state = true;
         P.lds_bytes = total_x2;
@@ -141,17 +140,32 @@ void make_plan(ldpc_code *c, int lds_limit)
         c->lds_syn_off = (int)(e_al + lp_al);
         c->lds_flag_off = (int)(e_al + lp_al + round_up(syn_bytes, 16));
         c->ws_frame_bytes = 0;
-    } else if (total <= (size_t)lds_limit) {
+        return true;
+    }
+    if (hint == LDPC_HINT_PAIRS)
+        return false;
+    // One lane per row: E at offset 0, L [block][row], the syndrome (LDS), or
+    // E and L in a global workspace slice per frame.
+    P.threads = (int)std::min<size_t>(1024, round_up((size_t)h.z, 64));
+    const size_t l_al = round_up((size_t)h.n_edges, 16);
+    const size_t total = e_al + l_al + syn_bytes;
+    c->lds_e_off = 0;
+    c->lds_l_off = (int)e_al;
+    c->lds_syn_off = (int)(e_al + l_al);
+    if ((hint == 0 || hint == LDPC_HINT_LDS) && total <= (size_t)lds_limit) {
         P.lds_state = true;
         P.lds_bytes = total;
         c->ws_frame_bytes = 0;
-    } else {
-        P.lds_state = false;
-        P.lds_bytes = syn_bytes;
-        c->lds_syn_off = 0;
-        c->ws_l_off = round_up((size_t)h.n * esize, 256);
-        c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.n_edges, 256);
+        return true;
     }
+    if (hint == LDPC_HINT_LDS)
+        return false;
+    P.lds_state = false;
+    P.lds_bytes = syn_bytes;
+    c->lds_syn_off = 0;
+    c->ws_l_off = round_up((size_t)h.n * esize, 256);
+    c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.n_edges, 256);
+    return true;
 }
 
 int check_device(const ldpc_code *code)
@@ -357,7 +371,10 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, con
     d.msg_max = hc.msg_max;
     d.e_max = hc.e_max;
     // leave room for the few bytes of static LDS the barrier reductions use
-    make_plan(c, lds_limit - 1024);
+    if (!make_plan(c, lds_limit - 1024, hc.kernel_hint)) {
+        ldpc_code_destroy(c);
+        return fail(LDPC_EUNSUPPORTED, "ldpc_code_create: the requested kernel family does not apply to this code");
+    }
     if (c->plan.split_dmax) {
         const std::vector<int32_t> st = split_tables(hc, c->plan.split_dmax);
         e = hipMalloc(&c->d_split, st.size() * sizeof(int32_t));

@@ -141,6 +141,11 @@ int build_host_code(const int32_t *base, int32_t mb, int32_t nb, int32_t z, cons
         err = "ldpc_code_create: offset_iters given without offsets";
         return LDPC_EINVAL;
     }
+    if (prm.kernel_hint < 0 || prm.kernel_hint > LDPC_HINT_SPLIT) {
+        err = fmt("ldpc_code_create: unknown kernel_hint %ld", prm.kernel_hint);
+        return LDPC_EINVAL;
+    }
+    h.kernel_hint = prm.kernel_hint;
     out = std::move(h);
     return LDPC_OK;
 }

@@ -32,7 +32,7 @@ struct HostCode {
     int32_t mb = 0, nb = 0, z = 0, n = 0, m = 0, n_blocks = 0, min_deg = 0, max_deg = 0;
     int64_t n_edges = 0;
     int32_t has_4cycles = 0;
-    int32_t msg_max = 63, e_max = 127, acc_bits = 8, cn_rule = 0, offset_iters = 0;
+    int32_t msg_max = 63, e_max = 127, acc_bits = 8, cn_rule = 0, offset_iters = 0, kernel_hint = 0;
     std::vector<int32_t> deg, blk_off, colbase, shift;
     std::vector<int8_t> offsets;
 };

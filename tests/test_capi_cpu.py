@@ -40,7 +40,7 @@ GOOD = I.make_base(5, 32, 32)
 
 @pytest.mark.parametrize("case", [
     "null_base", "z0", "mb_ge_nb", "shift_high", "shift_low", "zero_col", "row_deg1", "bad_acc",
-    "bad_msg", "bad_emax", "bad_rule", "off_iters0", "iters_no_off",
+    "bad_msg", "bad_emax", "bad_rule", "off_iters0", "iters_no_off", "bad_hint",
 ])
 def test_create_rejects_invalid_arguments(case):
     base = GOOD.copy()
@@ -66,18 +66,20 @@ def test_create_rejects_invalid_arguments(case):
         base[1, 0] = 1
         mb, nb = 2, 4
     elif case == "bad_acc":
-        prm = B.ldpc_params(0, 0, 12, 0, None, 0)
+        prm = B.ldpc_params(0, 0, 12, 0, None, 0, 0)
     elif case == "bad_msg":
-        prm = B.ldpc_params(200, 0, 0, 0, None, 0)
+        prm = B.ldpc_params(200, 0, 0, 0, None, 0, 0)
     elif case == "bad_emax":
-        prm = B.ldpc_params(0, 300, 8, 0, None, 0)
+        prm = B.ldpc_params(0, 300, 8, 0, None, 0, 0)
     elif case == "bad_rule":
-        prm = B.ldpc_params(0, 0, 0, 7, None, 0)
+        prm = B.ldpc_params(0, 0, 0, 7, None, 0, 0)
     elif case == "off_iters0":
         off = np.zeros(96, np.int8)
-        prm = B.ldpc_params(0, 0, 0, 0, off.ctypes.data, 0)
+        prm = B.ldpc_params(0, 0, 0, 0, off.ctypes.data, 0, 0)
+    elif case == "bad_hint":
+        prm = B.ldpc_params(0, 0, 0, 0, None, 0, 9)
     elif case == "iters_no_off":
-        prm = B.ldpc_params(0, 0, 0, 0, None, 3)
+        prm = B.ldpc_params(0, 0, 0, 0, None, 3, 0)
     rc, h = _create(base, mb, nb, z, prm)
     assert rc == B.LDPC_EINVAL
     assert not h.value
