@@ -148,6 +148,37 @@ def fer_sweep(wl, code, fracs, n_frames: int):
                           "efficiency_f": round(f_eff, 4)}), flush=True)
 
 
+def batched(wl, code, n_short, n_frames, steps, warmup):
+    """The same workload with many batches decoded per launch, under the fastest
+    of a few frame schedules (one workgroup per frame, or persistent workgroups
+    pulling frames from a queue); the schedule is picked by the autotuner."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+    from paper_1903_10107_amd import tune
+
+    fr = I.make_frames(code, n_frames, wl.qber, 10107, n_short=n_short)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cands = [tune.Schedule("auto", 0, "none", False), tune.Schedule("split", n_cu, "none", False),
+             tune.Schedule("split", 2 * n_cu, "none", False)]
+    best = tune.tune(code.base, code.z, fr.syn, fr.llr, wl.max_iter, acc_bits=wl.acc_bits, cache_path=None,
+                     cands=cands, reps=2)
+    sched = tune.Schedule(**best["schedule"])
+    run = tune.Runner(code.base, code.z, fr.syn, fr.llr, wl.max_iter, sched, acc_bits=wl.acc_bits)
+    ms = tune.time_ms(run, max(3, steps // 5), max(1, warmup))
+    bits, conv, iters = run.outputs()
+    correct, undetected = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
+    value = float(fr.key_bits()[correct].sum()) / (ms / 1e3) / 1e6
+    degs = [int((code.base[b] >= 0).sum()) for b in range(code.mb)]
+    tops = algorithmic_int_ops((code.z, degs), iters.sum()) / (ms / 1e3) / 1e12
+    return {"value": round(value, 2), "unit": "Mbit/s", "frames_per_launch": n_frames,
+            "ms_per_launch": round(ms, 4), "schedule": best["schedule"],
+            "schedules_tried": best["candidates"], "alu_frac": round(tops / ALU_PEAK_TOPS, 4),
+            "fer": round(float(n_frames - correct.sum()) / n_frames, 5),
+            "undetected_errors": int(undetected.sum()), "mean_iters": round(float(iters.mean()), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +188,8 @@ def main():
     ap.add_argument("--short-frac", type=float, default=None,
                     help="override the workload's shortened fraction (operating-point studies)")
     ap.add_argument("--frames", type=int, default=None, help="override the workload's batch size")
+    ap.add_argument("--batched-frames", type=int, default=4096,
+                    help="frames of the same workload decoded per launch for the batched figure (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fer-sweep", default="",
@@ -279,6 +312,8 @@ def main():
         "max_iters_in_batch": int(iters.max()),
         "paper_context": "57.6 Mbit/s at f=1.108 on a 4-core i7-6700HQ with its own irregular codes (context only)",
     }
+    if args.batched_frames:
+        out["batched"] = batched(wl, code, n_short, args.batched_frames, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

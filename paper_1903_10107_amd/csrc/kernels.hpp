@@ -112,9 +112,13 @@ inline hipError_t allow_max_lds()
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        // static LDS of the kernel (e.g. block reductions) counts against the same limit
+        hipFuncAttributes fa{};
+        if (e == hipSuccess)
+            e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(KERN));
         if (e == hipSuccess)
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(KERN), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    lim);
+                                    lim - (int)fa.sharedSizeBytes);
         return e;
     }();
     return once;
