@@ -74,7 +74,14 @@ typedef struct {
                                (for tuning and testing; results do not depend on it) */
 } ldpc_params;
 
-enum { LDPC_HINT_AUTO = 0, LDPC_HINT_GLOBAL = 1, LDPC_HINT_LDS = 2, LDPC_HINT_PAIRS = 3, LDPC_HINT_SPLIT = 4 };
+enum {
+    LDPC_HINT_AUTO = 0,
+    LDPC_HINT_GLOBAL = 1,
+    LDPC_HINT_LDS = 2,
+    LDPC_HINT_PAIRS = 3,
+    LDPC_HINT_SPLIT = 4,
+    LDPC_HINT_SPLIT_GLOBAL_L = 5
+};
 
 /* Build a code from a quasi-cyclic base matrix (Sec. 4.1).
  * base: HOST, int32 [mb][nb] row-major; -1 = zero block, 0..z-1 = circulant shift.
@@ -129,10 +136,20 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
  * LDPC_KERNEL_GLOBAL   state in a global-memory workspace, one lane per row;
  * LDPC_KERNEL_LDS      state in LDS, one lane per row;
  * LDPC_KERNEL_PAIRS    state in LDS, one lane per row pair (r, r + z/2), 16-bit packed;
- * LDPC_KERNEL_SPLIT    state in LDS, two lanes per row pair, 16-bit packed.
- * Also the workgroup size and the dynamic LDS bytes per workgroup. Any output
- * pointer may be NULL. */
-enum { LDPC_KERNEL_GLOBAL = 0, LDPC_KERNEL_LDS = 1, LDPC_KERNEL_PAIRS = 2, LDPC_KERNEL_SPLIT = 3 };
+ * LDPC_KERNEL_SPLIT    state in LDS, two lanes per row pair, 16-bit packed;
+ * LDPC_KERNEL_SPLIT_GLOBAL_L  as LDPC_KERNEL_SPLIT with E in LDS and the CN
+ *                      messages L in a global-memory slice per workgroup (codes
+ *                      whose L does not fit in LDS beside E).
+ * Automatic selection prefers them in the order SPLIT, SPLIT_GLOBAL_L, PAIRS,
+ * LDS, GLOBAL, taking the first that applies. Also the workgroup size and the
+ * dynamic LDS bytes per workgroup. Any output pointer may be NULL. */
+enum {
+    LDPC_KERNEL_GLOBAL = 0,
+    LDPC_KERNEL_LDS = 1,
+    LDPC_KERNEL_PAIRS = 2,
+    LDPC_KERNEL_SPLIT = 3,
+    LDPC_KERNEL_SPLIT_GLOBAL_L = 4
+};
 int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int32_t *lds_bytes);
 
 /* Device workspace needed by a decode of n_frames frames (0 when the whole
@@ -145,7 +162,9 @@ typedef struct {
     int32_t persistent_workgroups; /* > 0: launch that many workgroups; each takes the next
                                       frame from a device queue until none is left, so a CU that
                                       finishes a frame starts another at once. Needs the
-                                      LDPC_KERNEL_SPLIT kernel family (ldpc_code_plan). */
+                                      LDPC_KERNEL_SPLIT or LDPC_KERNEL_SPLIT_GLOBAL_L kernel
+                                      family (ldpc_code_plan); the latter's workspace then
+                                      holds one L slice per workgroup instead of per frame. */
     const int32_t *order;          /* DEVICE int32 [n_frames] or NULL: the order in which the
                                       queue hands out frames, a permutation of 0..n_frames-1
                                       (for instance hardest first); out-of-range entries are

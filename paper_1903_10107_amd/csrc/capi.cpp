@@ -98,8 +98,12 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     // Split (two lanes per row pair): power-of-two Z, forward-backward or min-sum
     // rule, no offsets, row degree <= 20. LDS: E plus a dummy block column, L as
     // [pair][layer][half][slot][lane] with an odd-dword pair stride, the
-    // syndrome, the lane table, three vote words and the queue slot.
-    if ((hint == 0 || hint == LDPC_HINT_SPLIT) && P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
+    // syndrome, the lane table, three vote words and the queue slot. When L does
+    // not fit, it moves to a global slice per workgroup (mb * Z * DMAX bytes)
+    // and only E, the syndrome, the table and the vote words stay in LDS.
+    P.split_global_l = false;
+    const bool split_hint = hint == LDPC_HINT_SPLIT || hint == LDPC_HINT_SPLIT_GLOBAL_L;
+    if ((hint == 0 || split_hint) && P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
         (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM)) {
         const int dmax = h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
         const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
@@ -107,22 +111,28 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
         const size_t l_sp = round_up((size_t)(h.z / 2) * stride, 16);
         const size_t tab = (size_t)h.mb * dh * 2 * 16;
         const size_t total_sp = e_sp + l_sp + round_up(syn_bytes, 16) + tab + 16;
-        if (total_sp <= (size_t)lds_limit) {
+        const size_t total_gl = e_sp + round_up(syn_bytes, 16) + tab + 16;
+        const bool lds_l = hint != LDPC_HINT_SPLIT_GLOBAL_L && total_sp <= (size_t)lds_limit;
+        const bool glob_l = !lds_l && hint != LDPC_HINT_SPLIT && total_gl <= (size_t)lds_limit;
+        if (lds_l || glob_l) {
+            const size_t l_len = lds_l ? l_sp : 0;
             P.split_dmax = dmax;
-            P.lds_state = true;
-            P.lds_bytes = total_sp;
+            P.split_global_l = glob_l;
+            P.lds_state = lds_l;
+            P.lds_bytes = lds_l ? total_sp : total_gl;
             P.threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
             c->l_stride = (int)stride;
             c->lds_l_off = (int)e_sp;
-            c->lds_syn_off = (int)(e_sp + l_sp);
-            c->lds_tab_off = (int)(e_sp + l_sp + round_up(syn_bytes, 16));
+            c->lds_syn_off = (int)(e_sp + l_len);
+            c->lds_tab_off = (int)(e_sp + l_len + round_up(syn_bytes, 16));
             c->lds_flag_off = (int)(c->lds_tab_off + tab);
-            c->ws_frame_bytes = 0;
+            c->ws_l_off = 0;
+            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * h.z * dmax, 256) : 0;
             c->lane_tab_bytes = tab;
             return true;
         }
     }
-    if (hint == LDPC_HINT_SPLIT)
+    if (split_hint)
         return false;
     // Pairs (one lane per row pair): even Z. LDS: E at offset 0, L as
     // [pair][block][half] with an odd-dword stride per pair, the syndrome, two
@@ -186,9 +196,13 @@ constexpr size_t kQueueBytes = 256;
 
 bool is_persistent(const ldpc_schedule *sched) { return sched && sched->persistent_workgroups > 0; }
 
+// Queue slot (persistent) plus one state slice per frame, or per persistent
+// workgroup for the split kernel, whose slices belong to workgroups.
 size_t workspace_need(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched)
 {
-    return (is_persistent(sched) ? kQueueBytes : 0) + code->ws_frame_bytes * (size_t)n_frames;
+    if (is_persistent(sched))
+        return kQueueBytes + code->ws_frame_bytes * (size_t)sched->persistent_workgroups;
+    return code->ws_frame_bytes * (size_t)n_frames;
 }
 
 int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
@@ -426,8 +440,10 @@ int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int
         return fail(LDPC_EINVAL, "ldpc_code_plan: code is NULL");
     const LaunchPlan &P = code->plan;
     if (kernel)
-        *kernel = P.split_dmax ? LDPC_KERNEL_SPLIT : P.pairs ? LDPC_KERNEL_PAIRS
-                                                 : P.lds_state ? LDPC_KERNEL_LDS : LDPC_KERNEL_GLOBAL;
+        *kernel = P.split_dmax ? (P.split_global_l ? LDPC_KERNEL_SPLIT_GLOBAL_L : LDPC_KERNEL_SPLIT)
+                  : P.pairs    ? LDPC_KERNEL_PAIRS
+                  : P.lds_state ? LDPC_KERNEL_LDS
+                                : LDPC_KERNEL_GLOBAL;
     if (threads)
         *threads = P.threads;
     if (lds_bytes)

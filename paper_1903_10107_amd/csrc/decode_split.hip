@@ -24,11 +24,17 @@ namespace qkdldpc {
 // addressed with absolute LDS addresses (the table holds them), so no base is
 // added per access. L of a row pair is laid out [layer][half][slot][lane].
 //
-// When every row pair has its own lane pair (Z/2 <= threads/2), the syndrome
-// test of the state after iteration t-1 is folded into layer 0 of iteration t:
-// layer 0 reads exactly that state, so its rows' parities come from the
-// loaded values; only when all of them hold are the other layers tested,
-// before layer 0 writes anything.
+// L lives in LDS when it fits beside E; otherwise (LG) it streams from a
+// global workspace slice per workgroup laid out [layer][row pair][lane][slot
+// byte pairs], so each lane moves its 2 x DH bytes with dword accesses and a
+// wave touches one contiguous run. The first iteration takes L = 0 without
+// reading it, so the slice needs no clearing between frames.
+//
+// When every row pair has a lane pair (Z/2 <= RPL x threads/2, with RPL row
+// pairs per lane pair), the syndrome test of the state after iteration t-1 is
+// folded into layer 0 of iteration t: layer 0 reads exactly that state, so its
+// rows' parities come from the loaded values; only when all of them hold are
+// the other layers tested, before layer 0 writes anything.
 // ---------------------------------------------------------------------------
 
 typedef int8_t __attribute__((address_space(3))) lds_i8;
@@ -94,6 +100,65 @@ __device__ __forceinline__ unsigned slot_addr(int4 te, int r, unsigned zm, unsig
     return ((((unsigned)r + (unsigned)te.x) & zm) << esh) | (unsigned)te.y;
 }
 
+// L slots of one lane for one row pair and layer.
+template <int DH, bool LG>
+struct LRef;
+
+// LDS, lane-interleaved: slot i of the lower half at p[2i], of the upper half at p[2DH + 2i]
+template <int DH>
+struct LRef<DH, false> {
+    int8_t *p;
+    __device__ __forceinline__ void load(s16x2 (&lk)[DH], bool) const
+    {
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            lk[i].x = (short)p[2 * i];
+            lk[i].y = (short)p[2 * DH + 2 * i];
+        }
+    }
+    __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
+    {
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            p[2 * i] = (int8_t)ln[i].x;
+            p[2 * DH + 2 * i] = (int8_t)ln[i].y;
+        }
+    }
+};
+
+// Global: DH/2 dwords; dword k holds slot 2k (lower half, upper half) in
+// bytes 0 and 1 and slot 2k+1 in bytes 2 and 3. zero: take L = 0 unread.
+template <int DH>
+struct LRef<DH, true> {
+    static_assert(DH % 2 == 0, "global L packs two slots per dword");
+    uint32_t *p;
+    __device__ __forceinline__ void load(s16x2 (&lk)[DH], bool zero) const
+    {
+        if (zero) {
+#pragma unroll
+            for (int i = 0; i < DH; ++i)
+                lk[i] = splat2(0);
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < DH / 2; ++k) {
+            const uint32_t w = p[k];
+            // bytes (b0, b1) -> halves (b0 << 8, b1 << 8), then an arithmetic shift per half
+            lk[2 * k] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x010c000cu)) >> (short)8;
+            lk[2 * k + 1] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x030c020cu)) >> (short)8;
+        }
+    }
+    __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
+    {
+#pragma unroll
+        for (int k = 0; k < DH / 2; ++k) {
+            const uint32_t a = __builtin_bit_cast(uint32_t, ln[2 * k]);
+            const uint32_t b = __builtin_bit_cast(uint32_t, ln[2 * k + 1]);
+            p[k] = (a & 0xffu) | ((a >> 8) & 0xff00u) | ((b & 0xffu) << 16) | ((b << 8) & 0xff000000u);
+        }
+    }
+};
+
 template <int DH>
 struct SplitRow {
     s16x2 e[DH], lk[DH];
@@ -101,9 +166,10 @@ struct SplitRow {
     int pm[DH];
 };
 
-template <int DMIN, int DMAX, typename ET>
-__device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const int8_t *__restrict__ Lp,
-                                           const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb)
+template <int DMIN, int DMAX, typename ET, bool LG>
+__device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const LRef<DMAX / 2, LG> &Lr,
+                                           const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb,
+                                           bool first)
 {
     constexpr int DH = DMAX / 2;
     constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
@@ -117,11 +183,8 @@ __device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const int8_t *
         ev.x = (short)lds_ld<ET>(a0);
         ev.y = (short)lds_ld<ET>(a0 ^ hzb);
         R.e[i] = ev;
-        s16x2 lv;
-        lv.x = (short)Lp[2 * i];
-        lv.y = (short)Lp[2 * DH + 2 * i];
-        R.lk[i] = lv;
     }
+    Lr.load(R.lk, first);
 }
 
 // XOR of the hard-decision sign bits of the row pair's slots held by this lane
@@ -136,9 +199,9 @@ __device__ __forceinline__ s16x2 split_e_parity(const SplitRow<DMAX / 2> &R)
     return own;
 }
 
-template <int DMIN, int DMAX, typename ET, int RULE>
-__device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DMAX / 2> &R, int8_t *__restrict__ Lp,
-                                             s16x2 syn, unsigned hzb)
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
+__device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DMAX / 2> &R,
+                                             const LRef<DMAX / 2, LG> &Lr, s16x2 syn, unsigned hzb)
 {
     constexpr int DH = DMAX / 2;
     constexpr int ACC = AccLim<ET>::value;
@@ -192,21 +255,21 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
         for (int i = 1; i < DH; ++i)
             out[i] = tau2(X[i - 1], W[DH - 1 - i]);
     }
+    s16x2 ln[DH];
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
         const s16x2 sg = (par ^ v[i]) >> (short)15;  // -1 in a half whose message is negative
         const s16x2 mg = as_s(out[i]);
-        const s16x2 ln = (mg ^ sg) - sg;
+        ln[i] = (mg ^ sg) - sg;
         // Eq. 9 under Alg. 2: halves whose stored |E| is E_max keep E
-        const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln), -em), em);
+        const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln[i]), -em), em);
         const s16x2 ae = vmax2(R.e[i], -R.e[i]);
         const s16x2 frozen = vmin2(em - ae, splat2(1)) - splat2(1);
         const s16x2 o = (frozen & R.e[i]) | (~frozen & ne);
         lds_st<ET>(R.a0[i], (ET)o.x);
         lds_st<ET>(R.a0[i] ^ hzb, (ET)o.y);
-        Lp[2 * i] = (int8_t)ln.x;
-        Lp[2 * DH + 2 * i] = (int8_t)ln.y;
     }
+    Lr.store(ln);
 }
 
 // 1 when some check row of layers [b0, b1) owned by this lane pair fails
@@ -250,11 +313,19 @@ struct SplitLds {
     int *flags;     // three vote words and one queue slot
 };
 
+// Row pairs per lane pair on the folded-check path: two for the short rows of
+// DMAX = 8 (Z up to 4096 with 1024 threads), one otherwise.
+template <int DMAX>
+constexpr int split_rpl() { return DMAX <= 8 ? 2 : 1; }
+
 // Decode frame f with one workgroup (the LDS table must already be staged).
-template <int DMIN, int DMAX, typename ET, int RULE>
-__device__ __forceinline__ void split_decode_frame(const DevCode &C, const DecodeArgs &A, const SplitLds<ET> &M, int f)
+// LG: L in the global slice Lg of this workgroup, else in LDS.
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
+__device__ __forceinline__ void split_decode_frame(const DevCode &C, const DecodeArgs &A, const SplitLds<ET> &M,
+                                                   uint8_t *Lg, int f)
 {
     constexpr int DH = DMAX / 2;
+    constexpr int RPL = split_rpl<DMAX>();
     constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int z = C.z, n = C.n, hz = z >> 1, h = tid & 1;
@@ -265,84 +336,116 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     const int4 *s_tab = M.tab;
     int *flags = M.flags;
     const int S = A.l_stride;
+    auto lref = [&](int b, int r) {
+        if constexpr (LG)
+            return LRef<DH, true>{reinterpret_cast<uint32_t *>(Lg + (((size_t)b * hz + r) * 2 + h) * (2 * DH))};
+        else
+            return LRef<DH, false>{L + r * S + h + b * 4 * DH};
+    };
 
-    // stage in: syndrome, E, L = 0, vote words
+    // stage in: syndrome, E, L = 0 (LDS only), vote words
     const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
     for (int i = tid; i < A.syn_bytes; i += nthr)
         s_syn[i] = syn[i];
     stage_llr<ET>(E, A.llr + (size_t)f * n, n, C.e_max < 127 ? C.e_max : 127, tid, nthr);
-    uint4 *L128 = reinterpret_cast<uint4 *>(L);
-    for (int w = tid; w < (hz * S) >> 4; w += nthr)
-        L128[w] = uint4{0, 0, 0, 0};
-    for (int w = ((hz * S) & ~15) + tid; w < hz * S; w += nthr)
-        L[w] = 0;
+    if constexpr (!LG) {
+        uint4 *L128 = reinterpret_cast<uint4 *>(L);
+        for (int w = tid; w < (hz * S) >> 4; w += nthr)
+            L128[w] = uint4{0, 0, 0, 0};
+        for (int w = ((hz * S) & ~15) + tid; w < hz * S; w += nthr)
+            L[w] = 0;
+    }
     if (tid < 3)
         flags[tid] = 0;
     __syncthreads();
     int vk = 0;
     int conv, iters = 0;
-    if (hz <= (nthr >> 1)) {
-        // one row pair per lane pair: the check is folded into layer 0
-        const int r = tid >> 1;
-        const bool act = r < hz;
-        int8_t *Lr = L + r * S + h;
-        conv = !block_vote(act ? split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 0, C.mb) : 0, flags, vk);
+    const int lp = tid >> 1, np = nthr >> 1;
+    if (hz <= RPL * np) {
+        // every row pair has a lane pair: the check is folded into layer 0
+        auto unsat_range = [&](int b0, int b1) {
+            int u = 0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int r = lp + k * np;
+                if (r < hz)
+                    u |= split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, b0, b1);
+            }
+            return u;
+        };
+        conv = !block_vote(unsat_range(0, C.mb), flags, vk);
         for (int t = 1; t <= A.max_iter && !conv; ++t) {
             {
-                SplitRow<DH> R;
-                const s16x2 syn0 = act ? syn_pair(s_syn, r, r + hz) : splat2(0);
-                if (act)
-                    split_load<DMIN, DMAX, ET>(R, Lr, s_tab + h, r, zm, hzb);
+                SplitRow<DH> R[RPL];
+                s16x2 syn0[RPL];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = lp + k * np;
+                    syn0[k] = splat2(0);
+                    if (r < hz) {
+                        syn0[k] = syn_pair(s_syn, r, r + hz);
+                        split_load<DMIN, DMAX, ET, LG>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1);
+                    }
+                }
                 if (t >= 2) {
                     int fail0 = 0;
-                    if (act) {
-                        const s16x2 own = split_e_parity<DMIN, DMAX>(R);
-                        const s16x2 pe = syn0 ^ own ^ swap_pair(own);
-                        fail0 = (pe.x | pe.y) < 0;
-                    }
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k)
+                        if (lp + k * np < hz) {
+                            const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
+                            const s16x2 pe = syn0[k] ^ own ^ swap_pair(own);
+                            fail0 |= (pe.x | pe.y) < 0;
+                        }
                     if (!block_vote(fail0, flags, vk)) {
-                        const int failr = act ? split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 1, C.mb) : 0;
-                        if (!block_vote(failr, flags, vk)) {
+                        if (!block_vote(unsat_range(1, C.mb), flags, vk)) {
                             conv = 1;
                             iters = t - 1;
                             break;
                         }
                     }
                 }
-                if (act)
-                    split_finish<DMIN, DMAX, ET, RULE>(C, R, Lr, syn0, hzb);
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = lp + k * np;
+                    if (r < hz)
+                        split_finish<DMIN, DMAX, ET, RULE, LG>(C, R[k], lref(0, r), syn0[k], hzb);
+                }
                 __syncthreads();
             }
             for (int b = 1; b < C.mb; ++b) {
-                if (act) {
-                    SplitRow<DH> R;
-                    int8_t *Lb = Lr + b * 4 * DH;
-                    split_load<DMIN, DMAX, ET>(R, Lb, s_tab + b * DH * 2 + h, r, zm, hzb);
-                    split_finish<DMIN, DMAX, ET, RULE>(C, R, Lb, syn_pair(s_syn, b * z + r, b * z + r + hz), hzb);
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = lp + k * np;
+                    if (r < hz) {
+                        SplitRow<DH> R;
+                        const auto Lr = lref(b, r);
+                        split_load<DMIN, DMAX, ET, LG>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1);
+                        split_finish<DMIN, DMAX, ET, RULE, LG>(C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz),
+                                                               hzb);
+                    }
                 }
                 __syncthreads();
             }
             iters = t;
         }
         if (!conv && A.max_iter > 0)
-            conv = !block_vote(act ? split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 0, C.mb) : 0, flags,
-                               vk);
+            conv = !block_vote(unsat_range(0, C.mb), flags, vk);
     } else {
-        // several row pairs per lane pair: separate check after every iteration
+        // more row pairs than that: separate check after every iteration
         auto unsat_all = [&]() {
             int u = 0;
-            for (int r = tid >> 1; r < hz; r += nthr >> 1)
+            for (int r = lp; r < hz; r += np)
                 u |= split_rows_unsat<DMIN, DMAX, ET>(C, s_syn, s_tab, h, r, 0, C.mb);
             return u;
         };
         conv = !block_vote(unsat_all(), flags, vk);
         for (int t = 1; t <= A.max_iter && !conv; ++t) {
             for (int b = 0; b < C.mb; ++b) {
-                for (int r = tid >> 1; r < hz; r += nthr >> 1) {
+                for (int r = lp; r < hz; r += np) {
                     SplitRow<DH> R;
-                    int8_t *Lb = L + r * S + h + b * 4 * DH;
-                    split_load<DMIN, DMAX, ET>(R, Lb, s_tab + b * DH * 2 + h, r, zm, hzb);
-                    split_finish<DMIN, DMAX, ET, RULE>(C, R, Lb, syn_pair(s_syn, b * z + r, b * z + r + hz), hzb);
+                    const auto Lr = lref(b, r);
+                    split_load<DMIN, DMAX, ET, LG>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1);
+                    split_finish<DMIN, DMAX, ET, RULE, LG>(C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz), hzb);
                 }
                 __syncthreads();
             }
@@ -373,12 +476,21 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             A.out_iters[f] = iters;
     }
     if (A.out_L) {
-        // canonical [block][row] layout
+        // canonical [block][row] layout; L was never written when no iteration ran
         const int ne = C.n_blocks * z;
         for (int e = tid; e < ne; e += nthr) {
             const int blk = e / z, row = e - blk * z;
             const int half = row >= hz, r = row - half * hz;
-            A.out_L[(size_t)f * ne + e] = L[r * S + A.blk2slot[blk] + half * 2 * DH];
+            const int v = A.blk2slot[blk];  // b * 4DH + 2 * slot + lane
+            int8_t x;
+            if constexpr (LG) {
+                const int b = v / (4 * DH), rem = v - b * 4 * DH;
+                x = iters == 0 ? (int8_t)0
+                               : (int8_t)Lg[(((size_t)b * hz + r) * 2 + (rem & 1)) * (2 * DH) + (rem & ~1) + half];
+            } else {
+                x = L[r * S + v + half * 2 * DH];
+            }
+            A.out_L[(size_t)f * ne + e] = x;
         }
     }
     if (A.out_E)
@@ -418,8 +530,16 @@ __device__ __forceinline__ void split_stage_table(const DevCode &C, const Decode
     }
 }
 
+// Global L slice of this workgroup (LG), indexed by workgroup so that
+// persistent workgroups reuse theirs from frame to frame.
+template <bool LG>
+__device__ __forceinline__ uint8_t *split_l_slice(const DecodeArgs &A)
+{
+    return LG ? A.ws + (size_t)blockIdx.x * A.ws_frame_bytes : nullptr;
+}
+
 // One workgroup per frame (grid = frames).
-template <int DMIN, int DMAX, typename ET, int RULE>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
 __global__ __launch_bounds__(1024) void k_decode_frame_split(DevCode C, DecodeArgs A)
 {
     SplitLds<ET> M;
@@ -433,20 +553,21 @@ __global__ __launch_bounds__(1024) void k_decode_frame_split(DevCode C, DecodeAr
         return;
     }
     split_stage_table<ET>(C, A, M, DMAX / 2);
-    split_decode_frame<DMIN, DMAX, ET, RULE>(C, A, M, f);
+    split_decode_frame<DMIN, DMAX, ET, RULE, LG>(C, A, M, split_l_slice<LG>(A), f);
 }
 
 // Persistent workgroups: each one takes the next position of a device queue
 // (atomic counter, reset to 0 by k_queue_reset before the launch), decodes
 // frame order[position] (or position), and stops once the queue is past the
 // last frame, which every wave of every workgroup reaches.
-template <int DMIN, int DMAX, typename ET, int RULE>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
 __global__ __launch_bounds__(1024) void k_decode_split_persistent(DevCode C, DecodeArgs A)
 {
     SplitLds<ET> M;
     if (!split_setup<ET>(C, A, M))
         return;
     split_stage_table<ET>(C, A, M, DMAX / 2);
+    uint8_t *Lg = split_l_slice<LG>(A);
     for (;;) {
         __syncthreads();  // the previous frame's stage-out is done with E and the queue slot
         if (threadIdx.x == 0)
@@ -457,20 +578,21 @@ __global__ __launch_bounds__(1024) void k_decode_split_persistent(DevCode C, Dec
             break;
         const int f = A.order ? A.order[q] : q;
         if ((unsigned)f < (unsigned)A.n_frames)
-            split_decode_frame<DMIN, DMAX, ET, RULE>(C, A, M, f);
+            split_decode_frame<DMIN, DMAX, ET, RULE, LG>(C, A, M, Lg, f);
     }
 }
 
 namespace {
 
-template <int DMIN, int DMAX, typename ET, int RULE>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
 hipError_t launch_one_split(const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
 {
     const bool persistent = A.persistent_wgs > 0;
-    auto kern = persistent ? k_decode_split_persistent<DMIN, DMAX, ET, RULE> : k_decode_frame_split<DMIN, DMAX, ET, RULE>;
+    auto kern = persistent ? k_decode_split_persistent<DMIN, DMAX, ET, RULE, LG>
+                           : k_decode_frame_split<DMIN, DMAX, ET, RULE, LG>;
     if (lds > 65536) {
-        hipError_t e = persistent ? allow_max_lds<k_decode_split_persistent<DMIN, DMAX, ET, RULE>>()
-                                  : allow_max_lds<k_decode_frame_split<DMIN, DMAX, ET, RULE>>();
+        hipError_t e = persistent ? allow_max_lds<k_decode_split_persistent<DMIN, DMAX, ET, RULE, LG>>()
+                                  : allow_max_lds<k_decode_frame_split<DMIN, DMAX, ET, RULE, LG>>();
         if (e != hipSuccess)
             return e;
     }
@@ -483,25 +605,25 @@ hipError_t launch_one_split(const DevCode &C, const DecodeArgs &A, int threads, 
     return hipGetLastError();
 }
 
-template <int DMIN, int DMAX, typename ET>
+template <int DMIN, int DMAX, typename ET, bool LG>
 hipError_t launch_rule_split(int rule, const DevCode &C, const DecodeArgs &A, int threads, size_t lds,
                              hipStream_t s)
 {
     if (rule == LDPC_RULE_MINSUM)
-        return launch_one_split<DMIN, DMAX, ET, kRuleMinSum>(C, A, threads, lds, s);
-    return launch_one_split<DMIN, DMAX, ET, kRuleRcbpFB>(C, A, threads, lds, s);
+        return launch_one_split<DMIN, DMAX, ET, kRuleMinSum, LG>(C, A, threads, lds, s);
+    return launch_one_split<DMIN, DMAX, ET, kRuleRcbpFB, LG>(C, A, threads, lds, s);
 }
 
-template <typename ET>
+template <typename ET, bool LG>
 hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
     switch (P.split_dmax) {
     case 8:
-        return P.min_deg >= 6 ? launch_rule_split<6, 8, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
-                              : launch_rule_split<2, 8, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+        return P.min_deg >= 6 ? launch_rule_split<6, 8, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
+                              : launch_rule_split<2, 8, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
     default:
-        return P.min_deg >= 19 ? launch_rule_split<19, 20, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
-                               : launch_rule_split<2, 20, ET>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+        return P.min_deg >= 19 ? launch_rule_split<19, 20, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
+                               : launch_rule_split<2, 20, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
     }
 }
 
@@ -509,7 +631,9 @@ hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs 
 
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
-    return P.acc_bits == 16 ? launch_split<int16_t>(P, C, A, s) : launch_split<int8_t>(P, C, A, s);
+    if (P.split_global_l)
+        return P.acc_bits == 16 ? launch_split<int16_t, true>(P, C, A, s) : launch_split<int8_t, true>(P, C, A, s);
+    return P.acc_bits == 16 ? launch_split<int16_t, false>(P, C, A, s) : launch_split<int8_t, false>(P, C, A, s);
 }
 
 } // namespace qkdldpc

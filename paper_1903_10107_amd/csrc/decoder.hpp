@@ -21,7 +21,7 @@ struct DecodeArgs {
     int8_t *out_L;        // [F][n_blocks][z] or nullptr
     int16_t *out_E;       // [F][n] or nullptr
     uint8_t *ws;          // global-memory state when it does not fit in LDS
-    size_t ws_frame_bytes;
+    size_t ws_frame_bytes; // bytes of one slice: per frame, or per workgroup (split kernel)
     size_t ws_l_off;      // offset of L inside a frame's workspace slice
     int syn_bytes, bit_bytes;
     int lds_e_off, lds_l_off, lds_syn_off, lds_flag_off;
@@ -43,6 +43,7 @@ struct LaunchPlan {
     bool pairs;       // packed kernel: one lane per row pair (r, r + Z/2); needs even Z and LDS state
     bool pow2;        // Z is a power of two
     int split_dmax;   // split kernel (two lanes per row pair) with this slot count, or 0
+    bool split_global_l; // split kernel with L in a global slice per workgroup (E stays in LDS)
     size_t lds_bytes; // dynamic LDS per workgroup
 };
 

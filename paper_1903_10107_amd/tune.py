@@ -52,13 +52,14 @@ def _key(base, z, n_frames, max_iter, acc_bits, has_difficulty) -> str:
 
 def candidates(n_cu: int, has_difficulty: bool) -> list[Schedule]:
     out = []
-    for kernel in ("split", "pairs", "lds", "global"):
+    for kernel in ("split", "split_global_l", "pairs", "lds", "global"):
         out.append(Schedule(kernel, 0, "none", False))
         out.append(Schedule(kernel, 0, "none", True))
-    for wgs in (n_cu, 2 * n_cu):
-        for order in (("none", "hardest_first") if has_difficulty else ("none",)):
-            for graph in (False, True):
-                out.append(Schedule("split", wgs, order, graph))
+    for kernel in B.PERSISTENT_FAMILIES:
+        for wgs in (n_cu, 2 * n_cu):
+            for order in (("none", "hardest_first") if has_difficulty else ("none",)):
+                for graph in (False, True):
+                    out.append(Schedule(kernel, wgs, order, graph))
     return out
 
 
@@ -68,7 +69,7 @@ class Runner:
     def __init__(self, base, z, syn, llr, max_iter, sched: Schedule, difficulty=None, acc_bits=0):
         import torch
         self.code = B.Code(base, z, acc_bits=acc_bits, kernel=sched.kernel)
-        if sched.persistent_workgroups and self.code.plan()["kernel"] != "split":
+        if sched.persistent_workgroups and self.code.plan()["kernel"] not in B.PERSISTENT_FAMILIES:
             raise B.LdpcError(B.LDPC_EUNSUPPORTED, "persistent schedule needs the split family")
         F = llr.shape[0]
         self.F = F

@@ -53,8 +53,13 @@ CASES = {
     "rule_minsum": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2}, {}),
     "minsum_offsets": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2, "offsets": "rand"}, {}),
     "rcbp_offsets": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"offsets": "rand"}, {}),
-    "deg6_n98304_global_state": (lambda: I.make_base(24, 48, 2048), 2048, 2, 0.04, 8, {},
+    "deg6_n98304_global_state": (lambda: I.make_base(24, 48, 2048), 2048, 2, 0.04, 8, {"kernel": "global"},
                                  {"short_frac": 0.1, "punct_frac": 0.1}),
+    "deg6_n98304_global_l": (lambda: I.make_base(24, 48, 2048), 2048, 3, 0.04, 12, {},
+                             {"short_frac": 0.1, "punct_frac": 0.1}),
+    "deg6_z2048_lds_rows_per_pair_2": (lambda: _rand_base(4, 8, 2048, 9), 2048, 4, 0.03, 20, {}, {}),
+    "deg6_z4096_global_l_rows_per_pair_4": (lambda: _rand_base(6, 12, 4096, 8), 4096, 2, 0.04, 10, {}, {}),
+    "n65536_deg20_global_l": (lambda: I.make_base(5, 32, 2048), 2048, 3, 0.02, 20, {}, {"short_frac": 0.33}),
     "max_iter0": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 0, {}, {}),
     "zero_error": (lambda: I.make_base(5, 32, 32), 32, 8, 1e-9, 50, {}, {}),
     "row_deg_24": (lambda: _rand_base(2, 24, 64, 7, 2), 64, 8, 0.01, 30, {}, {}),
@@ -108,7 +113,7 @@ def test_cases_cover_every_kernel_family(B):
         if ckw.get("offsets") == "rand":
             ckw["offsets"] = np.zeros((1, int((mk() >= 0).sum())), np.int8)
         seen.add(B.Code(mk(), z, **ckw).plan()["kernel"])
-    assert seen == {"global", "lds", "pairs", "split"}, seen
+    assert seen == {"global", "lds", "pairs", "split", "split_global_l"}, seen
 
 
 def test_llr_minus_128_is_read_as_minus_127(B):
