@@ -58,6 +58,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1903_10107_amd.build`")
+        # PyTorch ships its own HIP runtime under the same soname. Loading torch
+        # first makes the library bind to that runtime, so device pointers and
+        # streams from torch are valid in it; loading the library first would
+        # bring in a second HIP runtime, and torch's device init then fails.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.ldpc_code_create.restype = C.c_int

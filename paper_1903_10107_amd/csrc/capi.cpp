@@ -127,7 +127,8 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
             c->lds_tab_off = (int)(e_sp + l_len + round_up(syn_bytes, 16));
             c->lds_flag_off = (int)(c->lds_tab_off + tab);
             c->ws_l_off = 0;
-            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * h.z * dmax, 256) : 0;
+            // L of all layers plus one dummy chunk per lane of a pair
+            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * h.z * dmax + 2 * dmax, 256) : 0;
             c->lane_tab_bytes = tab;
             return true;
         }

@@ -141,12 +141,15 @@ struct LRef<DH, true> {
             return;
         }
 #pragma unroll
-        for (int k = 0; k < DH / 2; ++k) {
-            const uint32_t w = p[k];
-            // bytes (b0, b1) -> halves (b0 << 8, b1 << 8), then an arithmetic shift per half
-            lk[2 * k] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x010c000cu)) >> (short)8;
-            lk[2 * k + 1] = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x030c020cu)) >> (short)8;
-        }
+        for (int k = 0; k < DH / 2; ++k)
+            unpack(p[k], lk[2 * k], lk[2 * k + 1]);
+    }
+    // bytes (b0, b1, b2, b3) -> slots (b0, b1) and (b2, b3): each byte moves to
+    // the top of a 16-bit half, then an arithmetic shift per half
+    static __device__ __forceinline__ void unpack(uint32_t w, s16x2 &lo, s16x2 &hi)
+    {
+        lo = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x010c000cu)) >> (short)8;
+        hi = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x030c020cu)) >> (short)8;
     }
     __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
     {
@@ -166,10 +169,9 @@ struct SplitRow {
     int pm[DH];
 };
 
-template <int DMIN, int DMAX, typename ET, bool LG>
-__device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const LRef<DMAX / 2, LG> &Lr,
-                                           const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb,
-                                           bool first)
+template <int DMIN, int DMAX, typename ET>
+__device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *__restrict__ tab, int r, unsigned zm,
+                                             unsigned hzb)
 {
     constexpr int DH = DMAX / 2;
     constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
@@ -184,6 +186,14 @@ __device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const LRef<DMA
         ev.y = (short)lds_ld<ET>(a0 ^ hzb);
         R.e[i] = ev;
     }
+}
+
+template <int DMIN, int DMAX, typename ET, bool LG>
+__device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const LRef<DMAX / 2, LG> &Lr,
+                                           const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb,
+                                           bool first)
+{
+    split_load_e<DMIN, DMAX, ET>(R, tab, r, zm, hzb);
     Lr.load(R.lk, first);
 }
 
@@ -318,6 +328,10 @@ struct SplitLds {
 template <int DMAX>
 constexpr int split_rpl() { return DMAX <= 8 ? 2 : 1; }
 
+// Layers of prefetch distance for L in global memory (folded-check path).
+template <int DMAX>
+constexpr int split_pd() { return DMAX <= 8 ? 3 : 2; }
+
 // Decode frame f with one workgroup (the LDS table must already be staged).
 // LG: L in the global slice Lg of this workgroup, else in LDS.
 template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
@@ -361,7 +375,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     int vk = 0;
     int conv, iters = 0;
     const int lp = tid >> 1, np = nthr >> 1;
-    if (hz <= RPL * np) {
+    // global L needs more layers than the prefetch distance on this path
+    if (hz <= RPL * np && (!LG || C.mb > split_pd<DMAX>())) {
         // every row pair has a lane pair: the check is folded into layer 0
         auto unsat_range = [&](int b0, int b1) {
             int u = 0;
@@ -374,59 +389,160 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             return u;
         };
         conv = !block_vote(unsat_range(0, C.mb), flags, vk);
-        for (int t = 1; t <= A.max_iter && !conv; ++t) {
-            {
-                SplitRow<DH> R[RPL];
-                s16x2 syn0[RPL];
+        if constexpr (!LG) {
+            for (int t = 1; t <= A.max_iter && !conv; ++t) {
+                {
+                    SplitRow<DH> R[RPL];
+                    s16x2 syn0[RPL];
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = lp + k * np;
+                        syn0[k] = splat2(0);
+                        if (r < hz) {
+                            syn0[k] = syn_pair(s_syn, r, r + hz);
+                            split_load<DMIN, DMAX, ET, LG>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1);
+                        }
+                    }
+                    if (t >= 2) {
+                        int fail0 = 0;
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k)
+                            if (lp + k * np < hz) {
+                                const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
+                                const s16x2 pe = syn0[k] ^ own ^ swap_pair(own);
+                                fail0 |= (pe.x | pe.y) < 0;
+                            }
+                        if (!block_vote(fail0, flags, vk)) {
+                            if (!block_vote(unsat_range(1, C.mb), flags, vk)) {
+                                conv = 1;
+                                iters = t - 1;
+                                break;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = lp + k * np;
+                        if (r < hz)
+                            split_finish<DMIN, DMAX, ET, RULE, LG>(C, R[k], lref(0, r), syn0[k], hzb);
+                    }
+                    __syncthreads();
+                }
+                for (int b = 1; b < C.mb; ++b) {
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int r = lp + k * np;
+                        if (r < hz) {
+                            SplitRow<DH> R;
+                            const auto Lr = lref(b, r);
+                            split_load<DMIN, DMAX, ET, LG>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1);
+                            split_finish<DMIN, DMAX, ET, RULE, LG>(C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz),
+                                                                   hzb);
+                        }
+                    }
+                    __syncthreads();
+                }
+                iters = t;
+            }
+        } else {
+            // Global L, software-pipelined: one flat loop over the layer steps g
+            // of all iterations, unrolled by PD so that register slot j always
+            // serves the steps g = j (mod PD). After step g has unpacked its words
+            // from slot j, the slot is refilled with the words of step g + PD,
+            // whose latency then overlaps PD layers of work. That layer was last
+            // written at step g + PD - mb < g, before an earlier barrier, as
+            // mb > PD here. The first iteration takes L = 0 without reading it.
+            constexpr int NW = DH / 2;
+            constexpr int PD = split_pd<DMAX>();
+            // Every memory access of the loop is issued by every lane, so the
+            // number in flight is the same on all paths and the wait for a slot
+            // leaves the younger requests outstanding. Lanes without a row pair
+            // take row pair hz - 1 for their reads and write E to the dummy block
+            // column and L to a dummy chunk past the slice's layers.
+            const unsigned ebase = (unsigned)(uintptr_t)E;
+            const unsigned dummy_e = ebase + ((unsigned)(C.nb * z) << esh);
+            const unsigned rowbits = zm << esh;
+            // 32-bit byte offsets into the slice (a few hundred KB): the slice base
+            // stays uniform and the loads take their destination registers as is
+            const unsigned dummy_l = (unsigned)(C.mb * z * DMAX + h * (2 * DH));
+            int rr[RPL];
+            bool act[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                act[k] = lp + k * np < hz;
+                rr[k] = act[k] ? lp + k * np : hz - 1;
+            }
+            auto chunk = [&](int b, int k) {
+                const unsigned off = act[k] ? (unsigned)(((b * hz + rr[k]) * 2 + h) * (2 * DH)) : dummy_l;
+                return reinterpret_cast<uint32_t *>(Lg + off);
+            };
+            uint32_t pf[PD][RPL][NW] = {};
+            auto fetch = [&](uint32_t (&dst)[RPL][NW], int b) {
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    const int r = lp + k * np;
-                    syn0[k] = splat2(0);
-                    if (r < hz) {
-                        syn0[k] = syn_pair(s_syn, r, r + hz);
-                        split_load<DMIN, DMAX, ET, LG>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1);
-                    }
-                }
-                if (t >= 2) {
-                    int fail0 = 0;
+                    const uint32_t *c = chunk(b, k);
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k)
-                        if (lp + k * np < hz) {
-                            const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
-                            const s16x2 pe = syn0[k] ^ own ^ swap_pair(own);
-                            fail0 |= (pe.x | pe.y) < 0;
+                    for (int q = 0; q < NW; ++q)
+                        dst[k][q] = c[q];
+                }
+            };
+            int t = 1, b = 0;
+            bool done = conv || A.max_iter == 0;
+            while (!done) {
+#pragma unroll
+                for (int j = 0; j < PD; ++j) {
+                    if (done)
+                        break;
+                    SplitRow<DH> R[RPL];
+                    const s16x2 zero = splat2(0);
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        split_load_e<DMIN, DMAX, ET>(R[k], s_tab + b * DH * 2 + h, rr[k], zm, hzb);
+#pragma unroll
+                        for (int i = 0; i < DH; ++i)
+                            R[k].a0[i] = act[k] ? R[k].a0[i] : (R[k].a0[i] & rowbits) | dummy_e;
+#pragma unroll
+                        for (int q = 0; q < NW; ++q) {
+                            s16x2 lo, hi;
+                            LRef<DH, true>::unpack(pf[j][k][q], lo, hi);
+                            R[k].lk[2 * q] = t >= 2 ? lo : zero;
+                            R[k].lk[2 * q + 1] = t >= 2 ? hi : zero;
                         }
-                    if (!block_vote(fail0, flags, vk)) {
-                        if (!block_vote(unsat_range(1, C.mb), flags, vk)) {
+                    }
+                    if (b == 0 && t >= 2) {
+                        int fail0 = 0;
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) {
+                            if (act[k]) {
+                                const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
+                                const s16x2 pe = syn_pair(s_syn, rr[k], rr[k] + hz) ^ own ^ swap_pair(own);
+                                fail0 |= (pe.x | pe.y) < 0;
+                            }
+                        }
+                        if (!block_vote(fail0, flags, vk) && !block_vote(unsat_range(1, C.mb), flags, vk)) {
                             conv = 1;
                             iters = t - 1;
+                            done = true;
                             break;
                         }
                     }
-                }
+                    // refill the slot with step g + PD (loaded every time; unused data
+                    // of the first iteration or past the last one is ignored)
+                    fetch(pf[j], b + PD >= C.mb ? b + PD - C.mb : b + PD);
 #pragma unroll
-                for (int k = 0; k < RPL; ++k) {
-                    const int r = lp + k * np;
-                    if (r < hz)
-                        split_finish<DMIN, DMAX, ET, RULE, LG>(C, R[k], lref(0, r), syn0[k], hzb);
-                }
-                __syncthreads();
-            }
-            for (int b = 1; b < C.mb; ++b) {
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) {
-                    const int r = lp + k * np;
-                    if (r < hz) {
-                        SplitRow<DH> R;
-                        const auto Lr = lref(b, r);
-                        split_load<DMIN, DMAX, ET, LG>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1);
-                        split_finish<DMIN, DMAX, ET, RULE, LG>(C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz),
-                                                               hzb);
+                    for (int k = 0; k < RPL; ++k)
+                        split_finish<DMIN, DMAX, ET, RULE, true>(C, R[k], LRef<DH, true>{chunk(b, k)},
+                                                                 syn_pair(s_syn, b * z + rr[k], b * z + rr[k] + hz),
+                                                                 hzb);
+                    __syncthreads();
+                    if (++b == C.mb) {
+                        b = 0;
+                        iters = t;
+                        if (++t > A.max_iter)
+                            done = true;
                     }
                 }
-                __syncthreads();
             }
-            iters = t;
         }
         if (!conv && A.max_iter > 0)
             conv = !block_vote(unsat_range(0, C.mb), flags, vk);

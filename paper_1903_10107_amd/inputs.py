@@ -38,6 +38,7 @@ LLR_MAX = 127
 _STREAM_CODE = 1
 _STREAM_ORDER = 2
 _STREAM_FRAME = 3
+_STREAM_BUCKET = 4
 
 
 def _rng(seed: int, stream: int, index: int = 0) -> np.random.Generator:
@@ -285,6 +286,40 @@ def make_frames(code: Code, n_frames: int, qber, seed: int, *, n_short=0, n_punc
                   n_punct=pv, n_short=sv, key_mask=key_mask)
 
 
+def adapt_rate(fr: Frames, n_punct, n_short, order: np.ndarray | None = None) -> Frames:
+    """The same frames (x, errors, syndromes) under another puncture/shorten
+    split: identical to make_frames with these n_punct and n_short and the same
+    seed, since a frame's random draws do not depend on them. fr must carry no
+    puncturing or shortening itself."""
+    if np.any(fr.n_punct) or np.any(fr.n_short):
+        raise ValueError("adapt_rate starts from frames without puncturing or shortening")
+    code, F, n = fr.code, fr.n_frames, fr.code.n
+    pv = np.broadcast_to(np.asarray(n_punct, dtype=np.int64), (F,)).copy()
+    sv = np.broadcast_to(np.asarray(n_short, dtype=np.int64), (F,)).copy()
+    if np.any(sv + pv > n) or np.any(sv < 0) or np.any(pv < 0):
+        raise ValueError("n_short + n_punct must lie in [0, n]")
+    if order is None:
+        order = position_order(code)
+    llr, llr_f, y = fr.llr.copy(), fr.llr_f.copy(), fr.y.copy()
+    key_mask = np.ones((F, n), dtype=bool)
+    for p, s in {(int(a), int(b)) for a, b in zip(pv, sv)}:
+        rows = np.nonzero((pv == p) & (sv == s))[0]
+        if p:
+            pos = order[:p]
+            llr[np.ix_(rows, pos)] = 0
+            llr_f[np.ix_(rows, pos)] = 0.0
+            key_mask[np.ix_(rows, pos)] = False
+        if s:
+            pos = order[p:p + s]
+            xs = fr.x[np.ix_(rows, pos)]
+            llr[np.ix_(rows, pos)] = np.where(xs == 0, LLR_MAX, -LLR_MAX).astype(np.int8)
+            llr_f[np.ix_(rows, pos)] = np.where(xs == 0, SHORTENED_LLR_F, -SHORTENED_LLR_F)
+            y[np.ix_(rows, pos)] = xs
+            key_mask[np.ix_(rows, pos)] = False
+    return Frames(code=code, x=fr.x, y=y, syn=fr.syn, llr=llr, llr_f=llr_f, qber=fr.qber.copy(),
+                  n_punct=pv, n_short=sv, key_mask=key_mask)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads (shapes of the method's operating points)
 # ---------------------------------------------------------------------------
@@ -324,3 +359,23 @@ WORKLOADS = {
     # rate-adaptive mother code: 24x48 base, Z = 2048 (n = 98304, R = 1/2)
     "n98304_ragged": Workload("n98304_ragged", 24, 48, 2048, 2048, 0.04, 60),
 }
+
+# Ragged batch of the rate-adaptive mother code: each frame draws its QBER from
+# these buckets (uniformly, seeded) and is punctured / shortened to its
+# bucket's operating point, the largest rate whose frame error rate stayed at
+# or below 1e-2 in a bisection over 2048 seeded frames per probe (60 iterations;
+# paper_1903_10107_amd.rate). {qber: (n_punct, n_short)}
+RAGGED_QBERS = (0.01, 0.02, 0.04, 0.06, 0.08)
+RAGGED_POINTS = {0.01: (36959, 0), 0.02: (32255, 0), 0.04: (22655, 0), 0.06: (12095, 0), 0.08: (479, 0)}
+
+
+def make_ragged_frames(code: Code, n_frames: int, seed: int, points=None) -> Frames:
+    """Frames of one mother code with per-frame QBER, puncturing and shortening."""
+    points = RAGGED_POINTS if points is None else points
+    qs = np.array(sorted(points), dtype=np.float64)
+    # frame f's bucket depends only on (seed, f), not on the batch size
+    pick = np.array([_rng(seed, _STREAM_BUCKET, f).integers(0, len(qs)) for f in range(n_frames)], dtype=np.int64)
+    qv = qs[pick]
+    pv = np.array([points[float(q)][0] for q in qv], dtype=np.int64)
+    sv = np.array([points[float(q)][1] for q in qv], dtype=np.int64)
+    return make_frames(code, n_frames, qv, seed, n_short=sv, n_punct=pv)

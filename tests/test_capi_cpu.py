@@ -3,6 +3,7 @@ header declares, rejects invalid arguments on the host (before any device
 work), and its check-node arithmetic (compiled for the host from the same
 inline function the kernels use) equals the oracle's Alg. 1 table."""
 import ctypes as C
+import os
 
 import numpy as np
 import pytest
@@ -133,3 +134,16 @@ def test_host_packed_fold_equals_oracle(rule):
                                        ohi.ctypes.data) == 0
         assert np.array_equal(olo, O.cn_magnitudes(lo, rule, msg_max=127))
         assert np.array_equal(ohi, O.cn_magnitudes(hi, rule, msg_max=127))
+
+
+def test_one_hip_runtime_in_the_process():
+    """The library binds to the HIP runtime torch loads, whatever the import order."""
+    import subprocess
+    import sys
+    code = ("from paper_1903_10107_amd import binding as B; B.lib(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

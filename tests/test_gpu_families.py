@@ -32,6 +32,8 @@ CODES = {
     "n1024": (5, 32, 32, 24, 0.02, 0.0),
     "n32768_short": (5, 32, 1024, 4, 0.02, 0.33),
     "n6144_deg6": (12, 24, 256, 6, 0.04, 0.1),
+    "n16384_mb4_deg6": (4, 8, 2048, 4, 0.03, 0.0),
+    "n6144_mb3_deg6": (3, 6, 1024, 4, 0.03, 0.0),
 }
 
 

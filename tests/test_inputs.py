@@ -1,6 +1,7 @@
 """The seeded input generator: code shapes, syndrome = H x for an
 independently written H, LLR quantization, rate-adaptation positions."""
 import numpy as np
+import pytest
 
 from paper_1903_10107_amd import inputs as I
 from tests.dense_h import dense_h, gf2_matvec
@@ -71,3 +72,28 @@ def test_per_frame_qber_and_fixed_weight():
     code = I.Code(I.make_base(5, 32, 32), 32)
     fr = I.make_frames(code, 4, [0.01, 0.02, 0.04, 0.08], 4, fixed_weight=True)
     assert [(fr.x[f] ^ fr.y[f]).sum() for f in range(4)] == [10, 20, 41, 82]
+
+
+def test_adapt_rate_equals_generating_with_that_split():
+    code = I.Code(I.make_base(5, 32, 32), 32)
+    qv = np.array([0.01, 0.02, 0.04, 0.06, 0.08, 0.02])
+    pv = np.array([100, 0, 40, 0, 0, 100])
+    sv = np.array([0, 60, 10, 0, 200, 0])
+    ref = I.make_frames(code, 6, qv, 17, n_short=sv, n_punct=pv)
+    got = I.adapt_rate(I.make_frames(code, 6, qv, 17), pv, sv)
+    for k in ("x", "y", "syn", "llr", "llr_f", "n_punct", "n_short", "key_mask"):
+        assert np.array_equal(getattr(got, k), getattr(ref, k)), k
+    with pytest.raises(ValueError):
+        I.adapt_rate(ref, 0, 0)
+
+
+def test_ragged_frames_use_the_bucket_points():
+    code = I.Code(I.make_base(24, 48, 64), 64)
+    pts = {0.01: (900, 0), 0.04: (300, 0), 0.08: (0, 40)}
+    fr = I.make_ragged_frames(code, 40, 3, pts)
+    assert set(np.unique(fr.qber)) == set(pts)
+    for f in range(fr.n_frames):
+        assert (fr.n_punct[f], fr.n_short[f]) == pts[float(fr.qber[f])]
+        assert (fr.llr[f] == 0).sum() >= fr.n_punct[f]
+    small = I.make_ragged_frames(code, 10, 3, pts)
+    assert np.array_equal(small.qber, fr.qber[:10]) and np.array_equal(small.llr, fr.llr[:10])
