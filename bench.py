@@ -262,6 +262,16 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, args.steps, args.warmup)
         return
+    if args.workload == "n98304_ragged":
+        # the ragged rate-adaptive batch alone (for profiling its kernel)
+        torch.cuda.set_device(0)
+        r = ragged(args.ragged_frames or 2048, args.steps, args.warmup)
+        print(json.dumps({"metric": "corrected-key Mbit/s, ragged rate-adaptive batch, n=98304", "value": r["value"],
+                          "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r["ms_per_launch"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+                          "config": {"workload": "n98304_ragged"}, "ragged": r}), flush=True)
+        return
     wl = I.WORKLOADS[args.workload]
     if args.short_frac is not None or args.frames is not None:
         import dataclasses
