@@ -105,7 +105,7 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     const bool split_hint = hint == LDPC_HINT_SPLIT || hint == LDPC_HINT_SPLIT_GLOBAL_L;
     if ((hint == 0 || split_hint) && P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
         (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM)) {
-        const int dmax = h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
+        const int dmax = (h.min_deg == 6 && h.max_deg == 6) ? 6 : h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
         const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
         const size_t stride = (((size_t)h.mb * dh) | 1) * 4;
         const size_t l_sp = round_up((size_t)(h.z / 2) * stride, 16);
@@ -127,8 +127,8 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
             c->lds_tab_off = (int)(e_sp + l_len + round_up(syn_bytes, 16));
             c->lds_flag_off = (int)(c->lds_tab_off + tab);
             c->ws_l_off = 0;
-            // L of all layers plus one dummy chunk per lane of a pair
-            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * h.z * dmax + 2 * dmax, 256) : 0;
+            // L of all layers: one chunk of ceil(dh / 2) dwords per lane, row pair and layer
+            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * h.z * 4 * ((dh + 1) / 2), 256) : 0;
             c->lane_tab_bytes = tab;
             return true;
         }

@@ -126,11 +126,13 @@ struct LRef<DH, false> {
     }
 };
 
-// Global: DH/2 dwords; dword k holds slot 2k (lower half, upper half) in
-// bytes 0 and 1 and slot 2k+1 in bytes 2 and 3. zero: take L = 0 unread.
+// Global: ceil(DH/2) dwords (the chunk of one lane); dword k holds slot 2k
+// (lower half, upper half) in bytes 0 and 1 and slot 2k+1 in bytes 2 and 3
+// (zero past the last slot). zero: take L = 0 unread.
 template <int DH>
 struct LRef<DH, true> {
-    static_assert(DH % 2 == 0, "global L packs two slots per dword");
+    static constexpr int NW = (DH + 1) / 2;
+    static constexpr int BYTES = 4 * NW;
     uint32_t *p;
     __device__ __forceinline__ void load(s16x2 (&lk)[DH], bool zero) const
     {
@@ -141,8 +143,13 @@ struct LRef<DH, true> {
             return;
         }
 #pragma unroll
-        for (int k = 0; k < DH / 2; ++k)
-            unpack(p[k], lk[2 * k], lk[2 * k + 1]);
+        for (int k = 0; k < NW; ++k) {
+            s16x2 lo, hi;
+            unpack(p[k], lo, hi);
+            lk[2 * k] = lo;
+            if (2 * k + 1 < DH)
+                lk[2 * k + 1] = hi;
+        }
     }
     // bytes (b0, b1, b2, b3) -> slots (b0, b1) and (b2, b3): each byte moves to
     // the top of a 16-bit half, then an arithmetic shift per half
@@ -154,9 +161,9 @@ struct LRef<DH, true> {
     __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
     {
 #pragma unroll
-        for (int k = 0; k < DH / 2; ++k) {
+        for (int k = 0; k < NW; ++k) {
             const uint32_t a = __builtin_bit_cast(uint32_t, ln[2 * k]);
-            const uint32_t b = __builtin_bit_cast(uint32_t, ln[2 * k + 1]);
+            const uint32_t b = 2 * k + 1 < DH ? __builtin_bit_cast(uint32_t, ln[2 * k + 1]) : 0u;
             p[k] = (a & 0xffu) | ((a >> 8) & 0xff00u) | ((b & 0xffu) << 16) | ((b << 8) & 0xff000000u);
         }
     }
@@ -327,6 +334,7 @@ struct SplitLds {
 // DMAX = 8 (Z up to 4096 with 1024 threads), one otherwise.
 template <int DMAX>
 constexpr int split_rpl() { return DMAX <= 8 ? 2 : 1; }
+// (DMAX = 6 serves rows of degree exactly 6, DMAX = 8 degrees up to 8, DMAX = 20 up to 20.)
 
 // Layers of prefetch distance for L in global memory (folded-check path).
 template <int DMAX>
@@ -352,7 +360,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     const int S = A.l_stride;
     auto lref = [&](int b, int r) {
         if constexpr (LG)
-            return LRef<DH, true>{reinterpret_cast<uint32_t *>(Lg + (((size_t)b * hz + r) * 2 + h) * (2 * DH))};
+            return LRef<DH, true>{
+                reinterpret_cast<uint32_t *>(Lg + (((size_t)b * hz + r) * 2 + h) * LRef<DH, true>::BYTES)};
         else
             return LRef<DH, false>{L + r * S + h + b * 4 * DH};
     };
@@ -375,8 +384,9 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     int vk = 0;
     int conv, iters = 0;
     const int lp = tid >> 1, np = nthr >> 1;
-    // global L needs more layers than the prefetch distance on this path
-    if (hz <= RPL * np && (!LG || C.mb > split_pd<DMAX>())) {
+    // global L on this path: every lane pair owns RPL row pairs, and there are
+    // more layers than the prefetch distance
+    if (LG ? hz == RPL * np && C.mb > split_pd<DMAX>() : hz <= RPL * np) {
         // every row pair has a lane pair: the check is folded into layer 0
         auto unsat_range = [&](int b0, int b1) {
             int u = 0;
@@ -452,29 +462,21 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             // whose latency then overlaps PD layers of work. That layer was last
             // written at step g + PD - mb < g, before an earlier barrier, as
             // mb > PD here. The first iteration takes L = 0 without reading it.
-            constexpr int NW = DH / 2;
+            constexpr int NW = LRef<DH, true>::NW;
             constexpr int PD = split_pd<DMAX>();
-            // Every memory access of the loop is issued by every lane, so the
-            // number in flight is the same on all paths and the wait for a slot
-            // leaves the younger requests outstanding. Lanes without a row pair
-            // take row pair hz - 1 for their reads and write E to the dummy block
-            // column and L to a dummy chunk past the slice's layers.
-            const unsigned ebase = (unsigned)(uintptr_t)E;
-            const unsigned dummy_e = ebase + ((unsigned)(C.nb * z) << esh);
-            const unsigned rowbits = zm << esh;
-            // 32-bit byte offsets into the slice (a few hundred KB): the slice base
-            // stays uniform and the loads take their destination registers as is
-            const unsigned dummy_l = (unsigned)(C.mb * z * DMAX + h * (2 * DH));
+            // Every lane pair owns RPL row pairs here, so every memory access of
+            // the loop is issued by every lane: the number in flight is the same
+            // on all paths and the wait for a slot leaves the younger requests
+            // outstanding. 32-bit byte offsets into the slice (a few hundred KB)
+            // keep the slice base uniform, so the loads fill the slot registers
+            // in place.
             int rr[RPL];
-            bool act[RPL];
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                act[k] = lp + k * np < hz;
-                rr[k] = act[k] ? lp + k * np : hz - 1;
-            }
+            for (int k = 0; k < RPL; ++k)
+                rr[k] = lp + k * np;
             auto chunk = [&](int b, int k) {
-                const unsigned off = act[k] ? (unsigned)(((b * hz + rr[k]) * 2 + h) * (2 * DH)) : dummy_l;
-                return reinterpret_cast<uint32_t *>(Lg + off);
+                return reinterpret_cast<uint32_t *>(
+                    Lg + (unsigned)(((b * hz + rr[k]) * 2 + h) * LRef<DH, true>::BYTES));
             };
             uint32_t pf[PD][RPL][NW] = {};
             auto fetch = [&](uint32_t (&dst)[RPL][NW], int b) {
@@ -499,25 +501,21 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     for (int k = 0; k < RPL; ++k) {
                         split_load_e<DMIN, DMAX, ET>(R[k], s_tab + b * DH * 2 + h, rr[k], zm, hzb);
 #pragma unroll
-                        for (int i = 0; i < DH; ++i)
-                            R[k].a0[i] = act[k] ? R[k].a0[i] : (R[k].a0[i] & rowbits) | dummy_e;
-#pragma unroll
                         for (int q = 0; q < NW; ++q) {
                             s16x2 lo, hi;
                             LRef<DH, true>::unpack(pf[j][k][q], lo, hi);
                             R[k].lk[2 * q] = t >= 2 ? lo : zero;
-                            R[k].lk[2 * q + 1] = t >= 2 ? hi : zero;
+                            if (2 * q + 1 < DH)
+                                R[k].lk[2 * q + 1] = t >= 2 ? hi : zero;
                         }
                     }
                     if (b == 0 && t >= 2) {
                         int fail0 = 0;
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
-                            if (act[k]) {
-                                const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
-                                const s16x2 pe = syn_pair(s_syn, rr[k], rr[k] + hz) ^ own ^ swap_pair(own);
-                                fail0 |= (pe.x | pe.y) < 0;
-                            }
+                            const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
+                            const s16x2 pe = syn_pair(s_syn, rr[k], rr[k] + hz) ^ own ^ swap_pair(own);
+                            fail0 |= (pe.x | pe.y) < 0;
                         }
                         if (!block_vote(fail0, flags, vk) && !block_vote(unsat_range(1, C.mb), flags, vk)) {
                             conv = 1;
@@ -602,7 +600,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             if constexpr (LG) {
                 const int b = v / (4 * DH), rem = v - b * 4 * DH;
                 x = iters == 0 ? (int8_t)0
-                               : (int8_t)Lg[(((size_t)b * hz + r) * 2 + (rem & 1)) * (2 * DH) + (rem & ~1) + half];
+                               : (int8_t)Lg[(((size_t)b * hz + r) * 2 + (rem & 1)) * LRef<DH, true>::BYTES +
+                                            (rem & ~1) + half];
             } else {
                 x = L[r * S + v + half * 2 * DH];
             }
@@ -734,6 +733,8 @@ template <typename ET, bool LG>
 hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
     switch (P.split_dmax) {
+    case 6:
+        return launch_rule_split<6, 6, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
     case 8:
         return P.min_deg >= 6 ? launch_rule_split<6, 8, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
                               : launch_rule_split<2, 8, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);

@@ -28,20 +28,26 @@ def B():
     return binding
 
 
+# (mb, nb, z, frames, qber, shortened fraction, column weight): the split
+# kernel's slot variants (min, max row degree) are (19, 20), (2, 20), (6, 8),
+# (2, 8) and (6, 6).
 CODES = {
-    "n1024": (5, 32, 32, 24, 0.02, 0.0),
-    "n32768_short": (5, 32, 1024, 4, 0.02, 0.33),
-    "n6144_deg6": (12, 24, 256, 6, 0.04, 0.1),
-    "n16384_mb4_deg6": (4, 8, 2048, 4, 0.03, 0.0),
-    "n6144_mb3_deg6": (3, 6, 1024, 4, 0.03, 0.0),
+    "n1024": (5, 32, 32, 24, 0.02, 0.0, 3),
+    "n32768_short": (5, 32, 1024, 4, 0.02, 0.33, 3),
+    "n6144_deg6": (12, 24, 256, 6, 0.04, 0.1, 3),
+    "n16384_mb4_deg6": (4, 8, 2048, 4, 0.03, 0.0, 3),
+    "n6144_mb3_deg6": (3, 6, 1024, 4, 0.03, 0.0, 3),
+    "n3840_deg10_w2": (3, 15, 256, 6, 0.03, 0.0, 2),
+    "n2048_deg4_w2": (4, 8, 256, 6, 0.05, 0.0, 2),
+    "n18432_deg6to7": (4, 9, 2048, 4, 0.03, 0.0, 3),
 }
 
 
 @pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("name", list(CODES))
 def test_forced_family_matches_oracle(B, name, family):
-    mb, nb, z, F, q, short = CODES[name]
-    code = I.Code(I.make_base(mb, nb, z), z)
+    mb, nb, z, F, q, short, cw = CODES[name]
+    code = I.Code(I.make_base(mb, nb, z, cw), z)
     fr = I.make_frames(code, F, q, 1234 + z, n_short=int(short * code.n))
     try:
         gc = B.Code(code.base, z, kernel=family)
@@ -57,8 +63,8 @@ def test_forced_family_matches_oracle(B, name, family):
 
 
 def test_global_family_applies_to_every_code(B):
-    for name, (mb, nb, z, *_rest) in CODES.items():
-        assert B.Code(I.make_base(mb, nb, z), z, kernel="global").plan()["kernel"] == "global"
+    for name, (mb, nb, z, *_rest, cw) in CODES.items():
+        assert B.Code(I.make_base(mb, nb, z, cw), z, kernel="global").plan()["kernel"] == "global"
 
 
 def test_tuner_picks_an_agreeing_schedule(B, tmp_path):
