@@ -201,6 +201,59 @@ void ldpc_batch_destroy(ldpc_batch *batch);
 int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames,
                         uint8_t *out_syn, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Differentiable FP32 offset min-sum with learned offsets.
+ *
+ * The layered schedule of Sec. 2 (Eqs. 8 and 9) with the check node simplified
+ * to offset min-sum (the usual simplification of BP that the paper cites,
+ * Sec. 2) and one offset per iteration and base-matrix edge:
+ *   v_k = E_j - L_k;  L_k = sigma_k * max(min_{k' != k} |v_k'| - beta[t][blk_k], 0);  E_j = v_k + L_k
+ * with sigma_k the row's sign product times (-1)^{s_i} times sgn(v_k)
+ * (sgn(0) = +1). n_iter iterations run without early stopping. The training
+ * loss of a frame is sum_t w_t * sum_j softplus(-(1 - 2 x_j) E_j^(t)) / n, the
+ * binary cross-entropy of the soft values after every iteration t against the
+ * transmitted word x. The backward pass gives the gradient of
+ * sum_f dloss_f * loss_f with respect to the offsets (summed over frames) and,
+ * optionally, the channel LLRs. Ties between minima go to the lowest edge index;
+ * d|v|/dv = 0 at v = 0; the clamp at 0 passes gradient only where
+ * min - beta > 0. Results are deterministic (fixed-order reductions).
+ *
+ * The code's own decoder parameters (msg_max, e_max, rule, offsets) play no
+ * part here; only its base matrix and lifting do.
+ *
+ * Buffers (all DEVICE, caller-owned):
+ *   syndromes     uint8 [F][ceil(m/8)] packed LSB-first
+ *   llr           float [F][n], positive = bit 0
+ *   target_bits   uint8 [F][ceil(n/8)] the transmitted words x, packed LSB-first
+ *   beta          float [n_iter][n_blocks] (blocks in row-major base-matrix order)
+ *   loss_weights  float [n_iter], or NULL for all ones
+ *   tape          ldpc_oms_tape_bytes(code, F, n_iter) bytes: written by the
+ *                 forward pass, read by the backward pass (VN->CN values of
+ *                 every edge and iteration, soft values after every iteration)
+ *   workspace     ldpc_oms_workspace_bytes(code, F, n_iter) bytes (may be NULL
+ *                 when that is 0 for the forward pass): FP32 state of codes whose
+ *                 state does not fit in LDS, and per-frame offset gradients
+ * Returns LDPC_EINVAL for bad arguments (n_iter < 1, NULL pointers, short tape
+ * or workspace), LDPC_EDEVICE for launch failures. Asynchronous on stream.
+ * ------------------------------------------------------------------------ */
+size_t ldpc_oms_tape_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter);
+size_t ldpc_oms_workspace_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter);
+
+/* Forward pass. out_loss: float [F] per-frame loss, or NULL (then target_bits
+ * may be NULL); out_E: float [F][n] soft values after the last iteration, or NULL. */
+int ldpc_oms_forward(const ldpc_code *code, const uint8_t *syndromes, const float *llr,
+                     const uint8_t *target_bits, int32_t n_frames, int32_t n_iter, const float *beta,
+                     const float *loss_weights, float *out_loss, float *out_E, void *tape,
+                     size_t tape_bytes, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward pass over the tape of the forward pass with the same arguments.
+ * dloss: float [F]; out_dbeta: float [n_iter][n_blocks] (overwritten);
+ * out_dllr: float [F][n] or NULL. */
+int ldpc_oms_backward(const ldpc_code *code, const uint8_t *syndromes, const uint8_t *target_bits,
+                      int32_t n_frames, int32_t n_iter, const float *beta, const float *loss_weights,
+                      const float *dloss, const void *tape, size_t tape_bytes, float *out_dbeta,
+                      float *out_dllr, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Message describing the last error on this thread ("" if none). */
 const char *ldpc_last_error(void);
 

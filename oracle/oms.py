@@ -18,7 +18,9 @@ base-matrix edge):
 * Row i of layer b with edges k to columns j_k: v_k = E_{j_k} - L_k (Eq. 8);
   sigma_k = (-1)^{s_i} * prod_{k'} sgn(v_{k'}) * sgn(v_k) with sgn(0) = +1
   (syndrome decoding); L_k = sigma_k * max(min_{k' != k} |v_{k'}| - beta_{t,e(k)}, 0);
-  E_{j_k} = v_k + L_k (Eq. 9, no saturation in floating point).
+  E_{j_k} = v_k + L_k (Eq. 9, no saturation in floating point). Ties between
+  minima go to the lowest edge index (the paper does not address ties; the
+  choice only decides which tied input the gradient reaches).
 * T iterations, no early stop. Loss of a frame:
   sum_t w_t * sum_j softplus(-(1 - 2 x_j) * E_j^(t)) / n, with E^(t) the soft
   values after iteration t and x the transmitted word (binary cross-entropy of
@@ -45,6 +47,13 @@ def _layers(base):
                 blk += 1
         out.append((cols, shifts, blks))
     return out, blk
+
+
+def _first_min(a, ks, d):
+    """[F, 1, Z] index of the first minimum over dim 1 (no gradient)."""
+    with torch.no_grad():
+        lo = a.min(dim=1, keepdim=True).values
+        return torch.where(a == lo, ks, d).min(dim=1, keepdim=True).values
 
 
 def unpack_syndrome(syn_packed, m):
@@ -86,11 +95,14 @@ def oms_forward(base, z: int, syn_bits, llr, beta, x_bits, weights=None):
             total = (1.0 - 2.0 * syn[:, b, :]) * torch.prod(sg, dim=1)                 # [F, Z]
             sigma = total[:, None, :] * sg
             a = v.abs()
-            m1, i1 = a.min(dim=1)
-            masked = a.scatter(1, i1[:, None, :], float("inf"))
-            m2 = masked.min(dim=1).values
+            # minimum and second minimum; ties go to the lowest edge index
             ks = torch.arange(d)[None, :, None]
-            mex = torch.where(ks == i1[:, None, :], m2[:, None, :], m1[:, None, :])
+            i1 = _first_min(a, ks, d)
+            m1 = a.gather(1, i1)
+            masked = a.scatter(1, i1, float("inf"))
+            i2 = _first_min(masked, ks, d)
+            m2 = masked.gather(1, i2)
+            mex = torch.where(ks == i1, m2, m1)
             off = beta[t, blks][None, :, None]
             lnew = sigma * torch.relu(mex - off)
             for k, (c, s) in enumerate(zip(cols, shifts)):

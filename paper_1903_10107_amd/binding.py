@@ -102,6 +102,15 @@ def lib():
         L.ldpc_host_tau_table.argtypes = [vp]
         L.ldpc_host_fold_pair.restype = C.c_int
         L.ldpc_host_fold_pair.argtypes = [i32, vp, vp, i32, vp, vp]
+        L.ldpc_oms_tape_bytes.restype = C.c_size_t
+        L.ldpc_oms_tape_bytes.argtypes = [vp, i32, i32]
+        L.ldpc_oms_workspace_bytes.restype = C.c_size_t
+        L.ldpc_oms_workspace_bytes.argtypes = [vp, i32, i32]
+        L.ldpc_oms_forward.restype = C.c_int
+        L.ldpc_oms_forward.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+        L.ldpc_oms_backward.restype = C.c_int
+        L.ldpc_oms_backward.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, C.c_size_t, vp, vp, vp, C.c_size_t,
+                                        vp]
         _lib = L
     return _lib
 
@@ -349,3 +358,116 @@ def decode(code: Code, syn, llr, max_iter: int, *, want_state: bool = False, dev
     if want_state:
         out["L"], out["E"] = L.cpu().numpy(), E.cpu().numpy()
     return out
+
+
+# --- differentiable offset min-sum ---------------------------------------------
+
+def ldpc_oms_tape_bytes(code: Code, n_frames: int, n_iter: int) -> int:
+    return int(lib().ldpc_oms_tape_bytes(code.handle, int(n_frames), int(n_iter)))
+
+
+def ldpc_oms_workspace_bytes(code: Code, n_frames: int, n_iter: int) -> int:
+    return int(lib().ldpc_oms_workspace_bytes(code.handle, int(n_frames), int(n_iter)))
+
+
+def ldpc_oms_forward(code: Code, syndromes, llr, target_bits, n_frames: int, n_iter: int, beta, loss_weights,
+                     out_loss, out_E, tape, workspace=None, stream=None):
+    import torch
+    F, T = int(n_frames), int(n_iter)
+    sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+    p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+    p_llr = _dev_ptr(llr, torch.float32, (F, code.n), "llr")
+    p_x = _dev_ptr(target_bits, torch.uint8, (F, bb), "target_bits")
+    p_b = _dev_ptr(beta, torch.float32, (T, code.n_blocks), "beta")
+    p_w = _dev_ptr(loss_weights, torch.float32, (T,), "loss_weights")
+    p_l = _dev_ptr(out_loss, torch.float32, (F,), "out_loss")
+    p_e = _dev_ptr(out_E, torch.float32, (F, code.n), "out_E")
+    p_t = _dev_ptr(tape, torch.uint8, (ldpc_oms_tape_bytes(code, F, T),), "tape")
+    need = ldpc_oms_workspace_bytes(code, F, T)
+    p_ws = _dev_ptr(workspace, torch.uint8, (need,), "workspace") if workspace is not None else None
+    _check(lib().ldpc_oms_forward(code.handle, p_syn, p_llr, p_x, F, T, p_b, p_w, p_l, p_e, p_t, tape.numel(),
+                                  p_ws, workspace.numel() if workspace is not None else 0, _stream_ptr(stream)))
+
+
+def ldpc_oms_backward(code: Code, syndromes, target_bits, n_frames: int, n_iter: int, beta, loss_weights, dloss,
+                      tape, out_dbeta, out_dllr, workspace, stream=None):
+    import torch
+    F, T = int(n_frames), int(n_iter)
+    sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+    p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+    p_x = _dev_ptr(target_bits, torch.uint8, (F, bb), "target_bits")
+    p_b = _dev_ptr(beta, torch.float32, (T, code.n_blocks), "beta")
+    p_w = _dev_ptr(loss_weights, torch.float32, (T,), "loss_weights")
+    p_g = _dev_ptr(dloss, torch.float32, (F,), "dloss")
+    p_t = _dev_ptr(tape, torch.uint8, (ldpc_oms_tape_bytes(code, F, T),), "tape")
+    p_db = _dev_ptr(out_dbeta, torch.float32, (T, code.n_blocks), "out_dbeta")
+    p_dl = _dev_ptr(out_dllr, torch.float32, (F, code.n), "out_dllr")
+    need = ldpc_oms_workspace_bytes(code, F, T)
+    p_ws = _dev_ptr(workspace, torch.uint8, (need,), "workspace") if workspace is not None else None
+    _check(lib().ldpc_oms_backward(code.handle, p_syn, p_x, F, T, p_b, p_w, p_g, p_t, tape.numel(), p_db, p_dl,
+                                   p_ws, workspace.numel() if workspace is not None else 0, _stream_ptr(stream)))
+
+
+class OmsDecoder:
+    """Differentiable FP32 offset min-sum of one code: per-frame training loss
+    as a torch autograd function of the offsets beta [n_iter, n_blocks] and the
+    channel LLRs, computed by the library's forward and backward kernels."""
+
+    def __init__(self, base, z: int, n_iter: int, loss_weights=None):
+        import torch
+        self.code = Code(base, z)
+        self.n_iter = int(n_iter)
+        self.weights = None
+        if loss_weights is not None:
+            self.weights = torch.as_tensor(loss_weights, dtype=torch.float32).cuda().contiguous()
+
+    def loss(self, syndromes, llr, target_bits, beta, want_E: bool = False):
+        """Per-frame losses [F] (differentiable in beta and llr); with want_E also
+        the soft values after the last iteration [F, n] (no gradient)."""
+        out = _OmsFunction.apply(beta, llr, self, syndromes, target_bits)
+        return out if want_E else out[0]
+
+
+def _oms_function():
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, beta, llr, dec, syn, target):
+            F, T, code = llr.shape[0], dec.n_iter, dec.code
+            dev = llr.device
+            tape = torch.empty(ldpc_oms_tape_bytes(code, F, T), dtype=torch.uint8, device=dev)
+            need = ldpc_oms_workspace_bytes(code, F, T)
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+            loss = torch.empty(F, dtype=torch.float32, device=dev)
+            E = torch.empty((F, code.n), dtype=torch.float32, device=dev)
+            b = beta.detach().contiguous()
+            ldpc_oms_forward(code, syn, llr.detach().contiguous(), target, F, T, b, dec.weights, loss, E, tape, ws)
+            ctx.dec, ctx.syn, ctx.target, ctx.tape, ctx.ws, ctx.beta = dec, syn, target, tape, ws, b
+            ctx.mark_non_differentiable(E)
+            return loss, E
+
+        @staticmethod
+        def backward(ctx, dloss, _dE):
+            dec, code = ctx.dec, ctx.dec.code
+            F, T = ctx.syn.shape[0], dec.n_iter
+            dbeta = torch.empty((T, code.n_blocks), dtype=torch.float32, device=dloss.device)
+            dllr = torch.empty((F, code.n), dtype=torch.float32, device=dloss.device) if ctx.needs_input_grad[1] \
+                else None
+            ldpc_oms_backward(code, ctx.syn, ctx.target, F, T, ctx.beta, dec.weights, dloss.contiguous(), ctx.tape,
+                              dbeta, dllr, ctx.ws)
+            return dbeta, dllr, None, None, None
+
+    return _Fn
+
+
+class _LazyFn:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _oms_function()
+        return _LazyFn._fn.apply(*args)
+
+
+_OmsFunction = _LazyFn()

@@ -8,6 +8,7 @@
 
 #include "../../include/qkdldpc.h"
 #include "decoder.hpp"
+#include "oms.hpp"
 #include "qc_code.hpp"
 #include "rcbp.hpp"
 
@@ -28,6 +29,7 @@ struct ldpc_code {
     LaunchPlan plan{};
     size_t ws_frame_bytes = 0, ws_l_off = 0;
     int lds_e_off = 0, lds_l_off = 0, lds_syn_off = 0, lds_flag_off = 0, l_stride = 0;
+    int lds_limit = 0;
 };
 
 namespace {
@@ -304,6 +306,73 @@ int decode_impl(const ldpc_code *code, const uint8_t *syndromes, const int8_t *l
     return LDPC_OK;
 }
 
+// Differentiable offset min-sum: register slots, workgroup size and whether the
+// FP32 state (E and L, or their adjoints) fits in LDS beside the reduction
+// scratch and the syndrome.
+qkdldpc::OmsPlan oms_plan(const ldpc_code *c)
+{
+    const HostCode &h = c->h;
+    qkdldpc::OmsPlan P{};
+    P.dmax = h.max_deg <= 8 ? 8 : h.max_deg <= 20 ? 20 : 32;
+    // at most 512 threads: the kernels keep a row's slots in registers (256 VGPRs per lane)
+    P.threads = (int)std::min<size_t>(512, round_up((size_t)h.z, 64));
+    const size_t ne = (size_t)h.n_blocks * h.z;
+    const size_t fixed = (size_t)16 * P.dmax * sizeof(float) + round_up((size_t)(h.m + 7) / 8, 16);
+    const size_t st = ((size_t)h.n + ne) * sizeof(float);
+    P.lds_state = st + fixed <= (size_t)(c->lds_limit - 1024);
+    P.lds_bytes = (P.lds_state ? st : 0) + fixed;
+    return P;
+}
+
+size_t oms_tape_floats(const HostCode &h, int32_t n_iter)
+{
+    return (size_t)n_iter * ((size_t)h.n_blocks * h.z + h.n);
+}
+
+size_t oms_state_bytes(const ldpc_code *c, const qkdldpc::OmsPlan &P, int32_t n_frames)
+{
+    if (P.lds_state)
+        return 0;
+    return round_up(((size_t)c->h.n + (size_t)c->h.n_blocks * c->h.z) * sizeof(float) * n_frames, 256);
+}
+
+int oms_check(const ldpc_code *code, const char *who, const uint8_t *syndromes, int32_t n_frames, int32_t n_iter,
+              const float *beta, const void *tape, size_t tape_bytes)
+{
+    const std::string w(who);
+    if (!code)
+        return fail(LDPC_EINVAL, w + ": code is NULL");
+    if (n_frames < 0)
+        return fail(LDPC_EINVAL, w + ": n_frames < 0");
+    if (n_iter < 1)
+        return fail(LDPC_EINVAL, w + ": n_iter < 1");
+    if (!beta)
+        return fail(LDPC_EINVAL, w + ": beta is NULL");
+    if (n_frames > 0 && (!syndromes || !tape))
+        return fail(LDPC_EINVAL, w + ": syndromes and tape must be non-NULL");
+    if (tape_bytes < oms_tape_floats(code->h, n_iter) * sizeof(float) * (size_t)n_frames)
+        return fail(LDPC_EINVAL, w + ": tape smaller than ldpc_oms_tape_bytes");
+    return check_device(code);
+}
+
+qkdldpc::OmsArgs oms_args(const ldpc_code *code, const uint8_t *syndromes, const uint8_t *target_bits,
+                          int32_t n_frames, int32_t n_iter, const float *beta, const float *loss_weights, void *tape,
+                          void *workspace, const qkdldpc::OmsPlan &P)
+{
+    qkdldpc::OmsArgs A{};
+    A.syn = syndromes;
+    A.xbits = target_bits;
+    A.beta = beta;
+    A.weights = loss_weights;
+    A.n_frames = n_frames;
+    A.n_iter = n_iter;
+    A.syn_bytes = (code->h.m + 7) / 8;
+    A.bit_bytes = (code->h.n + 7) / 8;
+    A.tape = static_cast<float *>(tape);
+    A.state = P.lds_state ? nullptr : static_cast<float *>(workspace);
+    return A;
+}
+
 } // namespace
 
 struct ldpc_batch {
@@ -343,6 +412,7 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z, con
         return fail(LDPC_ENOMEM, "ldpc_code_create: out of host memory");
     c->h = std::move(h);
     c->device = dev;
+    c->lds_limit = lds_limit;
     const HostCode &hc = c->h;
     const size_t nt = 2 * (size_t)hc.mb + 3 * (size_t)hc.n_blocks;
     e = hipMalloc(&c->d_tables, nt * sizeof(int32_t));
@@ -599,6 +669,78 @@ int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_fr
         if (e != hipSuccess)
             return hip_fail("ldpc_syndrome_batch: kernel launch", e);
     }
+    return LDPC_OK;
+}
+
+size_t ldpc_oms_tape_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter)
+{
+    if (!code || n_frames < 0 || n_iter < 0)
+        return 0;
+    return oms_tape_floats(code->h, n_iter) * sizeof(float) * (size_t)n_frames;
+}
+
+size_t ldpc_oms_workspace_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter)
+{
+    if (!code || n_frames < 0 || n_iter < 0)
+        return 0;
+    const qkdldpc::OmsPlan P = oms_plan(code);
+    return oms_state_bytes(code, P, n_frames) + (size_t)n_frames * n_iter * code->h.n_blocks * sizeof(float);
+}
+
+int ldpc_oms_forward(const ldpc_code *code, const uint8_t *syndromes, const float *llr, const uint8_t *target_bits,
+                     int32_t n_frames, int32_t n_iter, const float *beta, const float *loss_weights, float *out_loss,
+                     float *out_E, void *tape, size_t tape_bytes, void *workspace, size_t workspace_bytes,
+                     void *stream)
+{
+    int rc = oms_check(code, "ldpc_oms_forward", syndromes, n_frames, n_iter, beta, tape, tape_bytes);
+    if (rc != LDPC_OK || n_frames == 0)
+        return rc;
+    if (!llr)
+        return fail(LDPC_EINVAL, "ldpc_oms_forward: llr is NULL");
+    if (out_loss && !target_bits)
+        return fail(LDPC_EINVAL, "ldpc_oms_forward: out_loss needs target_bits");
+    const qkdldpc::OmsPlan P = oms_plan(code);
+    const size_t need = oms_state_bytes(code, P, n_frames);
+    if (need && (!workspace || workspace_bytes < need))
+        return fail(LDPC_EINVAL, "ldpc_oms_forward: workspace smaller than ldpc_oms_workspace_bytes");
+    qkdldpc::OmsArgs A = oms_args(code, syndromes, target_bits, n_frames, n_iter, beta, loss_weights, tape,
+                                  workspace, P);
+    A.llr = llr;
+    A.out_loss = out_loss;
+    A.out_E = out_E;
+    hipError_t e = qkdldpc::launch_oms_forward(P, code->dev, A, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail("ldpc_oms_forward: kernel launch", e);
+    return LDPC_OK;
+}
+
+int ldpc_oms_backward(const ldpc_code *code, const uint8_t *syndromes, const uint8_t *target_bits, int32_t n_frames,
+                      int32_t n_iter, const float *beta, const float *loss_weights, const float *dloss,
+                      const void *tape, size_t tape_bytes, float *out_dbeta, float *out_dllr, void *workspace,
+                      size_t workspace_bytes, void *stream)
+{
+    int rc = oms_check(code, "ldpc_oms_backward", syndromes, n_frames, n_iter, beta, tape, tape_bytes);
+    if (rc != LDPC_OK)
+        return rc;
+    if (!out_dbeta)
+        return fail(LDPC_EINVAL, "ldpc_oms_backward: out_dbeta is NULL");
+    if (n_frames > 0 && (!target_bits || !dloss))
+        return fail(LDPC_EINVAL, "ldpc_oms_backward: target_bits and dloss must be non-NULL");
+    const qkdldpc::OmsPlan P = oms_plan(code);
+    const size_t need = ldpc_oms_workspace_bytes(code, n_frames, n_iter);
+    if (need && (!workspace || workspace_bytes < need))
+        return fail(LDPC_EINVAL, "ldpc_oms_backward: workspace smaller than ldpc_oms_workspace_bytes");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    qkdldpc::OmsArgs A = oms_args(code, syndromes, target_bits, n_frames, n_iter, beta, loss_weights,
+                                  const_cast<void *>(tape), workspace, P);
+    A.dloss = dloss;
+    A.dbeta_frames = reinterpret_cast<float *>(static_cast<uint8_t *>(workspace) + oms_state_bytes(code, P, n_frames));
+    A.dbeta = out_dbeta;
+    A.dllr = out_dllr;
+    // with no frames only the frame sum runs, writing a zero gradient
+    hipError_t e = qkdldpc::launch_oms_backward(P, code->dev, A, s);
+    if (e != hipSuccess)
+        return hip_fail("ldpc_oms_backward: kernel launch", e);
     return LDPC_OK;
 }
 

@@ -7,7 +7,7 @@ own code:
 * offsets above every magnitude: all messages vanish, so E stays the channel
   LLRs and the loss has a closed form with zero offset gradient;
 * one check row of degree 3, one iteration: loss and offset gradient written
-  out by hand;
+  out by hand, also with two tied minima (the tie goes to the lower index);
 * gradients equal FP64 central differences at generic (non-tied) points.
 """
 import math
@@ -106,3 +106,23 @@ def test_gradients_equal_central_differences():
         lm[fi, j] -= h
         fd = (f(beta, lp) - f(beta, lm)) / (2 * h)
         assert fd == pytest.approx(out["dllr"][fi, j], rel=1e-6, abs=1e-9)
+
+
+def test_tied_minima_send_the_gradient_to_the_lowest_edge():
+    base = np.array([[0, 0, 0]], dtype=np.int32)
+    llr = np.array([[1.0, -1.0, 2.0]])                       # |v| = 1, 1, 2: minima tied at edges 0, 1
+    x = np.array([[0, 0, 0]])
+    syn = np.array([[0]])
+    beta = np.array([[0.25, 0.25, 0.25]])
+    out = oms.oms_grad(base, 1, syn, llr, beta, x)
+    # sign product (+)(-)(+) = -1; sigma_k = -sgn(v_k) = (-, +, -)
+    # i1 = 0, i2 = 1: L_0 = -(|v_1| - b) = -0.75, L_1 = +(|v_0| - b) = 0.75, L_2 = -(|v_0| - b) = -0.75
+    E = np.array([1.0 - 0.75, -1.0 + 0.75, 2.0 - 0.75])
+    dsp = 1.0 / (1.0 + np.exp(E))                             # d softplus(-E)/d(-E), target bits 0
+    dE = -dsp / 3                                             # d loss / d E_j
+    # dE_k/dllr_j: identity, plus through the minima: L_0 reads |v_1|, L_1 and L_2 read |v_0|
+    # dL_0/dv_1 = sigma_0 * sgn(v_1) = (-1)(-1) = 1; dL_1/dv_0 = (+1)(+1) = 1; dL_2/dv_0 = (-1)(+1) = -1
+    dllr = dE.copy()
+    dllr[1] += dE[0] * 1.0
+    dllr[0] += dE[1] * 1.0 + dE[2] * -1.0
+    assert np.allclose(out["dllr"][0], dllr, rtol=1e-13, atol=1e-16)
