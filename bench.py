@@ -226,6 +226,89 @@ def ragged(n_frames, steps, warmup):
             "mean_iters": round(float(iters.mean()), 3), "buckets": per}
 
 
+def learned(steps_train, steps, warmup):
+    """Learned check-node offsets on the 5x32, Z = 256 code (n = 8192), QBER 2%,
+    36% shortened, 20 iterations: train per-iteration, per-edge offsets of the
+    FP32 offset min-sum with the library's forward and backward kernels (Adam,
+    512 frames per step from a fixed pool of 2048), quantize them to the
+    integer LLR step, and judge the integer decoder (min-sum + learned offsets)
+    against plain RCBP and plain min-sum on 4096 fresh frames."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import learn as LN
+    from paper_1903_10107_amd import metrics as M
+    from paper_1903_10107_amd import tune
+
+    T, F, q = 20, 512, 0.02
+    code = I.Code(I.make_base(5, 32, 256), 256)
+    ns = int(0.36 * code.n)
+    pool = I.make_frames(code, 4 * F, q, 4242, n_short=ns)
+    syn = torch.from_numpy(pool.syn).cuda()
+    llr = torch.from_numpy(LN.training_llr(pool)).cuda()
+    xb = torch.from_numpy(I.pack_bits(pool.x)).cuda()
+    w = torch.from_numpy((np.linspace(0.1, 1.0, T) ** 2).astype(np.float32)).cuda()
+    dec = B.OmsDecoder(code.base, code.z, T, w.cpu().numpy())
+    beta = torch.full((T, code.n_blocks), 0.3, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([beta], lr=0.02)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for step in range(steps_train):
+        sl = slice((step % 4) * F, (step % 4 + 1) * F)
+        opt.zero_grad(set_to_none=True)
+        loss = dec.loss(syn[sl], llr[sl], xb[sl], beta).mean()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            beta.clamp_(min=0.0)
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b) / max(steps_train, 1)
+    final_loss = float(loss.detach())
+
+    # the two kernels alone, on one batch
+    code_h = dec.code
+    tape = torch.empty(B.ldpc_oms_tape_bytes(code_h, F, T), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(max(B.ldpc_oms_workspace_bytes(code_h, F, T), 1), dtype=torch.uint8, device="cuda")
+    lo = torch.empty(F, device="cuda")
+    db = torch.empty((T, code.n_blocks), device="cuda")
+    bt = beta.detach().contiguous()
+    g = torch.full((F,), 1.0 / F, device="cuda")
+    fwd = lambda: B.ldpc_oms_forward(code_h, syn[:F], llr[:F], xb[:F], F, T, bt, w, lo, None, tape, ws)
+    bwd = lambda: B.ldpc_oms_backward(code_h, syn[:F], xb[:F], F, T, bt, w, g, tape, db, None, ws)
+    fwd_ms = tune.time_ms(fwd, max(3, steps // 5), max(1, warmup))
+    bwd_ms = tune.time_ms(bwd, max(3, steps // 5), max(1, warmup))
+    edge_iters = float(code.n_edges) * T * F
+    # FP32 operations per edge-iteration of the method: forward 14 (Eq. 8, |.|, sign
+    # parity, two-minimum update, exclusion select, offset, clamp, sign, Eq. 9)
+    fwd_tflops = 14 * edge_iters / (fwd_ms / 1e3) / 1e12
+
+    offsets = LN.int_offsets(bt.cpu().numpy())
+    judged = {}
+    for name, rule, off in (("rcbp", B.LDPC_RULE_RCBP_FB, None), ("minsum", B.LDPC_RULE_MINSUM, None),
+                            ("minsum_learned", B.LDPC_RULE_MINSUM, offsets)):
+        judged[name] = LN.evaluate(code, q, ns, max_iter=T, frames=4096, cn_rule=rule, offsets=off)
+    # throughput of the integer decoders on a 512-frame batch
+    fr = I.make_frames(code, F, q, 99, n_short=ns)
+    for name, rule, off in (("rcbp", B.LDPC_RULE_RCBP_FB, None), ("minsum_learned", B.LDPC_RULE_MINSUM, offsets)):
+        run = tune.Runner(code.base, code.z, fr.syn, fr.llr, T, tune.Schedule(), None, 0, cn_rule=rule, offsets=off)
+        ms = tune.time_ms(run, max(3, steps // 5), max(1, warmup))
+        bits, conv, _ = run.outputs()
+        ok, _ = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
+        judged[name]["mbit_s"] = round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2)
+        judged[name]["ms_per_batch"] = round(ms, 4)
+        judged[name]["kernel"] = run.code.plan()["kernel"]
+    return {"workload": "n8192_q2_learned", "code": "5x32 QC base, Z=256, column weight 3 (n=8192)",
+            "qber": q, "short_frac": 0.36, "iterations": T, "train_steps": steps_train, "frames_per_step": F,
+            "train_ms_per_step": round(train_ms, 3), "train_frames_per_s": round(F / (train_ms / 1e3), 1),
+            "final_loss": round(final_loss, 5), "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
+            "forward_fp32": {"achieved": round(fwd_tflops, 3), "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": round(fwd_tflops / 157.3, 4),
+                             "unit_ops": "14 FP32 ops per edge-iteration"},
+            "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "judged": judged}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +322,8 @@ def main():
                     help="frames of the same workload decoded per launch for the batched figure (0: skip)")
     ap.add_argument("--ragged-frames", type=int, default=2048,
                     help="frames of the ragged rate-adaptive batch (n = 98304) for its figure (0: skip)")
+    ap.add_argument("--learned-steps", type=int, default=150,
+                    help="training steps of the learned-offset figure (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fer-sweep", default="",
@@ -375,6 +460,8 @@ def main():
         out["batched"] = batched(wl, code, n_short, args.batched_frames, args.steps, args.warmup)
     if args.ragged_frames:
         out["ragged"] = ragged(args.ragged_frames, args.steps, args.warmup)
+    if args.learned_steps:
+        out["learned"] = learned(args.learned_steps, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -66,9 +66,9 @@ def candidates(n_cu: int, has_difficulty: bool) -> list[Schedule]:
 class Runner:
     """Device buffers and a callable that decodes the batch with one schedule."""
 
-    def __init__(self, base, z, syn, llr, max_iter, sched: Schedule, difficulty=None, acc_bits=0):
+    def __init__(self, base, z, syn, llr, max_iter, sched: Schedule, difficulty=None, acc_bits=0, **code_kw):
         import torch
-        self.code = B.Code(base, z, acc_bits=acc_bits, kernel=sched.kernel)
+        self.code = B.Code(base, z, acc_bits=acc_bits, kernel=sched.kernel, **code_kw)
         if sched.persistent_workgroups and self.code.plan()["kernel"] not in B.PERSISTENT_FAMILIES:
             raise B.LdpcError(B.LDPC_EUNSUPPORTED, "persistent schedule needs the split family")
         F = llr.shape[0]

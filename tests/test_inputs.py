@@ -97,3 +97,11 @@ def test_ragged_frames_use_the_bucket_points():
         assert (fr.llr[f] == 0).sum() >= fr.n_punct[f]
     small = I.make_ragged_frames(code, 10, 3, pts)
     assert np.array_equal(small.qber, fr.qber[:10]) and np.array_equal(small.llr, fr.llr[:10])
+
+
+def test_learned_offsets_quantize_to_the_llr_step():
+    from paper_1903_10107_amd import learn
+    d = I.DELTA
+    beta = np.array([[0.0, 0.49 * d, 0.51 * d, 1.5 * d + 1e-9, 100.0, -0.3]])
+    assert learn.int_offsets(beta).tolist() == [[0, 0, 1, 2, 63, 0]]
+    assert learn.int_offsets(beta, msg_max=31)[0, 4] == 31
