@@ -309,6 +309,36 @@ def learned(steps_train, steps, warmup):
             "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "judged": judged}
 
 
+def retry_figure(n_frames, extra=2048, step=512, max_rounds=12):
+    """Interactive reveal-and-retry on the ragged rate-adaptive batch: every frame
+    starts `extra` punctured positions above its bucket's operating point (a
+    higher rate), and each round Alice reveals `step` more punctured positions of
+    the frames that have not converged, until all converge."""
+    import numpy as np
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+    from paper_1903_10107_amd import retry
+
+    code = I.Code(I.make_base(24, 48, 2048), 2048)
+    pts = I.RAGGED_POINTS
+    base = I.make_ragged_frames(code, n_frames, 10107)
+    fr0 = I.make_frames(code, n_frames, base.qber, 10107)
+    p0 = np.array([pts[float(q)][0] + extra for q in base.qber], dtype=np.int64)
+    fr = I.adapt_rate(fr0, np.minimum(p0, code.n - code.m - 1), np.zeros(n_frames, dtype=np.int64))
+    res = retry.reconcile(code, fr, 60, reveal_step=step, max_rounds=max_rounds)
+    out = res.summary(code, fr.qber)
+    out.update({"workload": "n98304_ragged retry", "start": f"operating point + {extra} punctured",
+                "reveal_step": step, "max_rounds": max_rounds, "buckets": {}})
+    for q in sorted(pts):
+        sel = fr.qber == q
+        out["buckets"][f"{q:.2f}"] = {
+            "frames": int(sel.sum()), "mean_rounds": round(float(res.rounds[sel].mean()), 2),
+            "fer": round(float(1 - res.correct[sel].mean()), 5),
+            "f_retry": round(float(res.efficiency[sel & res.correct].mean()), 4) if (sel & res.correct).any() else None,
+            "f_fixed_point": round(float(M.efficiency(code.n, code.m, pts[q][0], pts[q][1], q)), 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +354,8 @@ def main():
                     help="frames of the ragged rate-adaptive batch (n = 98304) for its figure (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=150,
                     help="training steps of the learned-offset figure (0: skip)")
+    ap.add_argument("--retry-frames", type=int, default=2048,
+                    help="frames of the reveal-and-retry figure on the ragged batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fer-sweep", default="",
@@ -462,6 +494,8 @@ def main():
         out["ragged"] = ragged(args.ragged_frames, args.steps, args.warmup)
     if args.learned_steps:
         out["learned"] = learned(args.learned_steps, args.steps, args.warmup)
+    if args.retry_frames:
+        out["retry"] = retry_figure(args.retry_frames)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

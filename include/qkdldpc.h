@@ -201,6 +201,24 @@ void ldpc_batch_destroy(ldpc_batch *batch);
 int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames,
                         uint8_t *out_syn, void *stream);
 
+/* Interactive rate adaptation (Sec. 4.1): after a failed decode Alice reveals
+ * the values of further positions of a frame (typically punctured ones, which
+ * then count as shortened), and Bob decodes again. For each listed frame
+ * frame_ids[i] (i < k) and each of its r positions positions[i * r + q], the
+ * LLR becomes the shortened value: -127 if values[i * r + q] != 0 (bit 1), else
+ * +127. Ids outside [0, n_frames) and positions outside [0, n) are skipped, so
+ * rows can be padded with -1.
+ *   llr        DEVICE int8 [n_frames][n], updated in place
+ *   frame_ids  DEVICE int32 [k]
+ *   positions  DEVICE int32 [k][r]
+ *   values     DEVICE uint8 [k][r], the revealed bits (0 or 1)
+ * Returns LDPC_EINVAL for NULL pointers (when k * r > 0), negative counts or
+ * k * r >= 2^31.
+ * Asynchronous on stream. */
+int ldpc_reveal_batch(const ldpc_code *code, int8_t *llr, int32_t n_frames, const int32_t *frame_ids,
+                      int32_t k, const int32_t *positions, const uint8_t *values, int32_t r,
+                      void *stream);
+
 /* ------------------------------------------------------------------------
  * Differentiable FP32 offset min-sum with learned offsets.
  *

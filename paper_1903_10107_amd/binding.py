@@ -102,6 +102,8 @@ def lib():
         L.ldpc_host_tau_table.argtypes = [vp]
         L.ldpc_host_fold_pair.restype = C.c_int
         L.ldpc_host_fold_pair.argtypes = [i32, vp, vp, i32, vp, vp]
+        L.ldpc_reveal_batch.restype = C.c_int
+        L.ldpc_reveal_batch.argtypes = [vp, vp, i32, vp, i32, vp, vp, i32, vp]
         L.ldpc_oms_tape_bytes.restype = C.c_size_t
         L.ldpc_oms_tape_bytes.argtypes = [vp, i32, i32]
         L.ldpc_oms_workspace_bytes.restype = C.c_size_t
@@ -358,6 +360,22 @@ def decode(code: Code, syn, llr, max_iter: int, *, want_state: bool = False, dev
     if want_state:
         out["L"], out["E"] = L.cpu().numpy(), E.cpu().numpy()
     return out
+
+
+def ldpc_reveal_batch(code: Code, llr, n_frames: int, frame_ids, positions, values, stream=None):
+    """Set the LLRs of revealed positions to +-127 (see include/qkdldpc.h).
+    frame_ids int32 [k], positions int32 [k, r], values uint8 [k, r], all on the GPU."""
+    import torch
+    F = int(n_frames)
+    k = int(frame_ids.numel()) if frame_ids is not None else 0
+    r = int(positions.shape[1]) if positions is not None and positions.dim() == 2 else 0
+    if k == 0 or r == 0:
+        return
+    p_llr = _dev_ptr(llr, torch.int8, (F, code.n), "llr")
+    p_id = _dev_ptr(frame_ids, torch.int32, (k,), "frame_ids")
+    p_pos = _dev_ptr(positions, torch.int32, (k, r), "positions")
+    p_val = _dev_ptr(values, torch.uint8, (k, r), "values")
+    _check(lib().ldpc_reveal_batch(code.handle, p_llr, F, p_id, k, p_pos, p_val, r, _stream_ptr(stream)))
 
 
 # --- differentiable offset min-sum ---------------------------------------------

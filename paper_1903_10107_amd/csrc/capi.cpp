@@ -672,6 +672,29 @@ int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_fr
     return LDPC_OK;
 }
 
+int ldpc_reveal_batch(const ldpc_code *code, int8_t *llr, int32_t n_frames, const int32_t *frame_ids, int32_t k,
+                      const int32_t *positions, const uint8_t *values, int32_t r, void *stream)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_reveal_batch: code is NULL");
+    if (n_frames < 0 || k < 0 || r < 0)
+        return fail(LDPC_EINVAL, "ldpc_reveal_batch: n_frames, k and r must be >= 0");
+    if ((long long)k * r >= (1LL << 31))
+        return fail(LDPC_EINVAL, "ldpc_reveal_batch: k * r must be below 2^31");
+    if ((long long)k * r == 0)
+        return LDPC_OK;
+    if (!llr || !frame_ids || !positions || !values)
+        return fail(LDPC_EINVAL, "ldpc_reveal_batch: llr, frame_ids, positions and values must be non-NULL");
+    int rc = check_device(code);
+    if (rc != LDPC_OK)
+        return rc;
+    hipError_t e = qkdldpc::launch_reveal(llr, code->h.n, n_frames, frame_ids, k, positions, values, r,
+                                          reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail("ldpc_reveal_batch: kernel launch", e);
+    return LDPC_OK;
+}
+
 size_t ldpc_oms_tape_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter)
 {
     if (!code || n_frames < 0 || n_iter < 0)

@@ -53,5 +53,7 @@ hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const Deco
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s);
 hipError_t launch_queue_reset(int *queue, hipStream_t s);
+hipError_t launch_reveal(int8_t *llr, int n, int n_frames, const int32_t *frame_ids, int k, const int32_t *positions,
+                         const uint8_t *values, int r, hipStream_t s);
 
 } // namespace qkdldpc

@@ -42,6 +42,35 @@ hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, 
     return hipGetLastError();
 }
 
+// Interactive rate adaptation (Sec. 4.1): Alice reveals the values of some
+// positions of listed frames; Bob's LLRs there become the shortened value,
+// +-127 with the sign of the revealed bit. Positions outside [0, n) and frame
+// ids outside [0, n_frames) are skipped.
+__global__ __launch_bounds__(256) void k_reveal(int8_t *__restrict__ llr, int n, int n_frames,
+                                                const int32_t *__restrict__ frame_ids, int k,
+                                                const int32_t *__restrict__ positions,
+                                                const uint8_t *__restrict__ values, int r)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)k * r)
+        return;
+    const int i = (int)(q / r);
+    const int f = frame_ids[i];
+    const int j = positions[q];
+    if ((unsigned)f < (unsigned)n_frames && (unsigned)j < (unsigned)n)
+        llr[(size_t)f * n + j] = values[q] ? (int8_t)-127 : (int8_t)127;
+}
+
+hipError_t launch_reveal(int8_t *llr, int n, int n_frames, const int32_t *frame_ids, int k, const int32_t *positions,
+                         const uint8_t *values, int r, hipStream_t s)
+{
+    const long long total = (long long)k * r;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_reveal, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, llr, n,
+                       n_frames, frame_ids, k, positions, values, r);
+    return hipGetLastError();
+}
+
 // Reset the frame queue of a persistent launch (a kernel, not a memset, so that
 // the pair can be captured in a graph and replayed).
 __global__ void k_queue_reset(int *queue)
