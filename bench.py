@@ -122,9 +122,10 @@ def copy_calibration(nbytes: int, steps: int, warmup: int):
                       "read_plus_write_GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}), flush=True)
 
 
-def fer_sweep(wl, code, fracs, n_frames: int):
+def fer_sweep(wl, code, fracs, n_frames: int, qbers=None):
     """Frame error rate, iterations and efficiency at several shortened
-    fractions of the workload's code and QBER, decoding n_frames per point."""
+    fractions of the workload's code, at its QBER or at each of qbers,
+    decoding n_frames per point."""
     import numpy as np
     import torch
     from paper_1903_10107_amd import binding as B
@@ -133,15 +134,15 @@ def fer_sweep(wl, code, fracs, n_frames: int):
 
     torch.cuda.set_device(0)
     gc = B.Code(code.base, code.z, acc_bits=wl.acc_bits)
-    for frac in fracs:
+    for q, frac in [(q, f) for q in (qbers or [wl.qber]) for f in fracs]:
         ns = int(round(frac * code.n))
-        fr = I.make_frames(code, n_frames, wl.qber, 777, n_short=ns)
+        fr = I.make_frames(code, n_frames, q, 777, n_short=ns)
         got = B.decode(gc, fr.syn, fr.llr, wl.max_iter)
         ok, und = M.frame_outcomes(fr.x, I.unpack_bits(got["bits"], code.n), got["conv"])
         fails = int(n_frames - ok.sum())
         lo, hi = M.wilson_interval(fails, n_frames)
         f_eff = float(np.mean(M.efficiency(code.n, code.m, fr.n_punct, fr.n_short, fr.qber)))
-        print(json.dumps({"workload": wl.name, "short_frac": frac, "shortened": ns, "frames": n_frames,
+        print(json.dumps({"workload": wl.name, "qber": q, "short_frac": frac, "shortened": ns, "frames": n_frames,
                           "fer": fails / n_frames, "fer_ci95": [round(lo, 5), round(hi, 5)],
                           "undetected": int(und.sum()), "mean_iters": round(float(got["iters"].mean()), 3),
                           "p99_iters": float(np.percentile(got["iters"], 99)),
@@ -360,6 +361,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fer-sweep", default="",
                     help="comma-separated shortened fractions: print FER, iterations and f at each")
+    ap.add_argument("--qber-sweep", default="",
+                    help="comma-separated QBERs for --fer-sweep (default: the workload's)")
     ap.add_argument("--sweep-frames", type=int, default=4096)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="instead of decoding, run a plain device copy of BYTES bytes per step "
@@ -396,7 +399,8 @@ def main():
                                  frames=wl.frames if args.frames is None else args.frames)
     code = wl.code()
     if args.fer_sweep:
-        fer_sweep(wl, code, [float(v) for v in args.fer_sweep.split(",")], args.sweep_frames)
+        fer_sweep(wl, code, [float(v) for v in args.fer_sweep.split(",")], args.sweep_frames,
+                  [float(v) for v in args.qber_sweep.split(",")] if args.qber_sweep else None)
         return
     n_short = int(round(wl.short_frac * code.n))
     fr = I.make_frames(code, wl.frames, wl.qber, 10107, n_short=n_short)
