@@ -252,7 +252,9 @@ int ldpc_reveal_batch(const ldpc_code *code, int8_t *llr, int32_t n_frames, cons
  *                 when that is 0 for the forward pass): FP32 state of codes whose
  *                 state does not fit in LDS, and per-frame offset gradients
  * Returns LDPC_EINVAL for bad arguments (n_iter < 1, NULL pointers, short tape
- * or workspace), LDPC_EDEVICE for launch failures. Asynchronous on stream.
+ * or workspace), LDPC_EUNSUPPORTED when the offset table (n_iter x n_blocks
+ * floats) does not fit in on-chip memory, LDPC_EDEVICE for launch failures.
+ * Asynchronous on stream.
  * ------------------------------------------------------------------------ */
 size_t ldpc_oms_tape_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter);
 size_t ldpc_oms_workspace_bytes(const ldpc_code *code, int32_t n_frames, int32_t n_iter);

@@ -306,21 +306,25 @@ int decode_impl(const ldpc_code *code, const uint8_t *syndromes, const int8_t *l
     return LDPC_OK;
 }
 
-// Differentiable offset min-sum: register slots, workgroup size and whether the
-// FP32 state (E and L, or their adjoints) fits in LDS beside the reduction
-// scratch and the syndrome.
-qkdldpc::OmsPlan oms_plan(const ldpc_code *c)
+// Differentiable offset min-sum: register slots, workgroup size (four lanes per
+// row, up to 1024 threads) and whether the FP32 state (E and L, or their
+// adjoints) fits in LDS beside the offset table, the reduction scratch and the
+// syndrome. fits is false when even the offset table does not fit.
+qkdldpc::OmsPlan oms_plan(const ldpc_code *c, int32_t n_iter, bool *fits = nullptr)
 {
     const HostCode &h = c->h;
     qkdldpc::OmsPlan P{};
     P.dmax = h.max_deg <= 8 ? 8 : h.max_deg <= 20 ? 20 : 32;
-    // at most 512 threads: the kernels keep a row's slots in registers (256 VGPRs per lane)
-    P.threads = (int)std::min<size_t>(512, round_up((size_t)h.z, 64));
+    P.threads = (int)std::min<size_t>(1024, round_up(4 * (size_t)h.z, 64));
     const size_t ne = (size_t)h.n_blocks * h.z;
-    const size_t fixed = (size_t)16 * P.dmax * sizeof(float) + round_up((size_t)(h.m + 7) / 8, 16);
+    const size_t fixed = (size_t)16 * P.dmax * sizeof(float) + (size_t)std::max(n_iter, 0) * h.n_blocks * sizeof(float) +
+                         round_up((size_t)(h.m + 7) / 8, 16);
     const size_t st = ((size_t)h.n + ne) * sizeof(float);
-    P.lds_state = st + fixed <= (size_t)(c->lds_limit - 1024);
+    const size_t limit = (size_t)(c->lds_limit - 1024);
+    P.lds_state = st + fixed <= limit;
     P.lds_bytes = (P.lds_state ? st : 0) + fixed;
+    if (fits)
+        *fits = fixed <= limit;
     return P;
 }
 
@@ -352,6 +356,10 @@ int oms_check(const ldpc_code *code, const char *who, const uint8_t *syndromes, 
         return fail(LDPC_EINVAL, w + ": syndromes and tape must be non-NULL");
     if (tape_bytes < oms_tape_floats(code->h, n_iter) * sizeof(float) * (size_t)n_frames)
         return fail(LDPC_EINVAL, w + ": tape smaller than ldpc_oms_tape_bytes");
+    bool fits = false;
+    (void)oms_plan(code, n_iter, &fits);
+    if (!fits)
+        return fail(LDPC_EUNSUPPORTED, w + ": the offset table (n_iter x n_blocks floats) does not fit in LDS");
     return check_device(code);
 }
 
@@ -706,7 +714,7 @@ size_t ldpc_oms_workspace_bytes(const ldpc_code *code, int32_t n_frames, int32_t
 {
     if (!code || n_frames < 0 || n_iter < 0)
         return 0;
-    const qkdldpc::OmsPlan P = oms_plan(code);
+    const qkdldpc::OmsPlan P = oms_plan(code, n_iter);
     return oms_state_bytes(code, P, n_frames) + (size_t)n_frames * n_iter * code->h.n_blocks * sizeof(float);
 }
 
@@ -722,7 +730,7 @@ int ldpc_oms_forward(const ldpc_code *code, const uint8_t *syndromes, const floa
         return fail(LDPC_EINVAL, "ldpc_oms_forward: llr is NULL");
     if (out_loss && !target_bits)
         return fail(LDPC_EINVAL, "ldpc_oms_forward: out_loss needs target_bits");
-    const qkdldpc::OmsPlan P = oms_plan(code);
+    const qkdldpc::OmsPlan P = oms_plan(code, n_iter);
     const size_t need = oms_state_bytes(code, P, n_frames);
     if (need && (!workspace || workspace_bytes < need))
         return fail(LDPC_EINVAL, "ldpc_oms_forward: workspace smaller than ldpc_oms_workspace_bytes");
@@ -749,7 +757,7 @@ int ldpc_oms_backward(const ldpc_code *code, const uint8_t *syndromes, const uin
         return fail(LDPC_EINVAL, "ldpc_oms_backward: out_dbeta is NULL");
     if (n_frames > 0 && (!target_bits || !dloss))
         return fail(LDPC_EINVAL, "ldpc_oms_backward: target_bits and dloss must be non-NULL");
-    const qkdldpc::OmsPlan P = oms_plan(code);
+    const qkdldpc::OmsPlan P = oms_plan(code, n_iter);
     const size_t need = ldpc_oms_workspace_bytes(code, n_frames, n_iter);
     if (need && (!workspace || workspace_bytes < need))
         return fail(LDPC_EINVAL, "ldpc_oms_backward: workspace smaller than ldpc_oms_workspace_bytes");

@@ -15,6 +15,14 @@
 // v, and propagates the adjoints of E and L. Ties go to the lowest edge index,
 // d|v|/dv is 0 at v = 0 and the offset's clamp passes gradient only where
 // min - beta > 0. Reductions run in a fixed order, so results are deterministic.
+//
+// Four lanes (a quad) share a row: lane q holds the row's edges
+// k in [q * S, (q + 1) * S), S = DMAX / 4, in registers. The row's sign parity,
+// minimum (with its edge index), second minimum (with its index) are combined
+// across the quad with two xor-shuffles; ties compare (value, index), so the
+// lowest index wins as in the sequential definition. L (and its adjoint) and the
+// tape's v are laid out per layer as [row][edge] (layer b starts at
+// blk_off[b] * Z), so a quad reads and writes contiguous words.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -25,6 +33,8 @@
 namespace qkdldpc {
 
 namespace {
+
+constexpr int kQuad = 4;
 
 __device__ __forceinline__ float wave_sum(float x)
 {
@@ -58,12 +68,45 @@ __device__ __forceinline__ float block_sum(float x, float *red)
     return s;
 }
 
-struct OmsState {
-    float *E, *L;      // E [n], L [n_blocks * Z] (forward) or their adjoints (backward)
-    uint8_t *syn;      // packed syndrome of the frame
-    float *red;        // reduction scratch
+// (m1, i1): smallest |v| and its edge index; (m2, i2): smallest among the other
+// edges and its index; par: xor of the sign bits and the syndrome bit.
+struct RowMin {
+    float m1, m2;
+    int i1, i2, par;
 };
 
+__device__ __forceinline__ bool lex_less(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
+
+// Combine with the quad partner at xor distance o.
+__device__ __forceinline__ RowMin quad_combine(RowMin a, int o)
+{
+    RowMin b;
+    b.m1 = __shfl_xor(a.m1, o, 64);
+    b.m2 = __shfl_xor(a.m2, o, 64);
+    b.i1 = __shfl_xor(a.i1, o, 64);
+    b.i2 = __shfl_xor(a.i2, o, 64);
+    b.par = __shfl_xor(a.par, o, 64);
+    RowMin r;
+    r.par = a.par ^ b.par;
+    const bool aw = lex_less(a.m1, a.i1, b.m1, b.i1);
+    const RowMin &w = aw ? a : b, &l = aw ? b : a;
+    r.m1 = w.m1;
+    r.i1 = w.i1;
+    // second: the better of the winner's second and the loser's first
+    const bool s2 = lex_less(w.m2, w.i2, l.m1, l.i1);
+    r.m2 = s2 ? w.m2 : l.m1;
+    r.i2 = s2 ? w.i2 : l.i1;
+    return r;
+}
+
+struct OmsState {
+    float *E, *L;      // E [n], L [n_blocks * Z] (forward) or their adjoints (backward)
+    float *beta;       // offsets [T][n_blocks] staged in LDS
+    float *red;        // reduction scratch
+    uint8_t *syn;      // packed syndrome of the frame
+};
+
+// LDS: [state if LDS] [beta T * n_blocks] [red] [syndrome]
 __device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A, bool lds, int red_floats)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -78,25 +121,37 @@ __device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A
         S.E = A.state + (size_t)blockIdx.x * (C.n + ne);
         S.L = S.E + C.n;
     }
+    S.beta = reinterpret_cast<float *>(p);
+    p += (size_t)A.n_iter * C.n_blocks * sizeof(float);
     S.red = reinterpret_cast<float *>(p);
     p += (size_t)red_floats * sizeof(float);
     S.syn = p;
     return S;
 }
 
+__device__ __forceinline__ void stage_common(const DevCode &C, const OmsArgs &A, const OmsState &S)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const uint8_t *syn = A.syn + (size_t)blockIdx.x * A.syn_bytes;
+    for (int i = tid; i < A.syn_bytes; i += nthr)
+        S.syn[i] = syn[i];
+    for (int i = tid; i < A.n_iter * C.n_blocks; i += nthr)
+        S.beta[i] = A.beta[i];
+}
+
 } // namespace
 
 template <int DMAX, bool LDS>
-__global__ __launch_bounds__(512) void k_oms_forward(DevCode C, OmsArgs A)
+__global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
 {
+    constexpr int SL = DMAX / kQuad;  // edges per lane
     const int f = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
     const int z = C.z, n = C.n, T = A.n_iter;
+    const int q = tid & (kQuad - 1), rq = tid / kQuad, nq = nthr / kQuad;
     const size_t ne = (size_t)C.n_blocks * z;
     OmsState S = oms_state(C, A, LDS, 16);
     float *E = S.E, *L = S.L;
-    const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
-    for (int i = tid; i < A.syn_bytes; i += nthr)
-        S.syn[i] = syn[i];
+    stage_common(C, A, S);
     const float *llr = A.llr + (size_t)f * n;
     for (int j = tid; j < n; j += nthr)
         E[j] = llr[j];
@@ -107,45 +162,63 @@ __global__ __launch_bounds__(512) void k_oms_forward(DevCode C, OmsArgs A)
     const uint8_t *xb = A.xbits ? A.xbits + (size_t)f * A.bit_bytes : nullptr;
     float loss = 0.f;
     for (int t = 0; t < T; ++t) {
-        const float *bt = A.beta + (size_t)t * C.n_blocks;
+        const float *bt = S.beta + t * C.n_blocks;
         float *tv = tape + (size_t)t * (ne + n);
         for (int b = 0; b < C.mb; ++b) {
             const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
-            for (int r = tid; r < z; r += nthr) {
-                float v[DMAX];
-                int col[DMAX];
-                const int i = b * z + r;
-                int par = (S.syn[i >> 3] >> (i & 7)) & 1;
-                float m1 = INFINITY, m2 = INFINITY;
-                int i1 = 0;
+            const size_t lb = (size_t)o * z;  // layer b's [row][edge] block
+            // all lanes of a quad take part in the shuffles, so the row loop is
+            // uniform across the quad (rows past Z are masked per lane)
+            for (int r0 = 0; r0 < z; r0 += nq) {
+                const int r = r0 + rq;
+                const bool act = r < z;
+                float v[SL];
+                int col[SL];
+                RowMin M;
+                M.m1 = M.m2 = INFINITY;
+                M.i1 = M.i2 = DMAX;
+                M.par = 0;
+                if (act && q == 0) {
+                    const int i = b * z + r;
+                    M.par = (S.syn[i >> 3] >> (i & 7)) & 1;
+                }
 #pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    if (k < d) {
+                for (int s = 0; s < SL; ++s) {
+                    const int k = q * SL + s;
+                    v[s] = 0.f;
+                    col[s] = 0;
+                    if (act && k < d) {
                         const int blk = o + k;
                         const int j = ldc(C.colbase, blk) + rot(r, ldc(C.shift, blk), z);
-                        const float vk = E[j] - L[(size_t)blk * z + r];
-                        tv[(size_t)blk * z + r] = vk;
-                        v[k] = vk;
-                        col[k] = j;
-                        par ^= vk < 0.f;
+                        const size_t le = lb + (size_t)r * d + k;
+                        const float vk = E[j] - L[le];
+                        tv[le] = vk;
+                        v[s] = vk;
+                        col[s] = j;
+                        M.par ^= vk < 0.f;
                         const float a = fabsf(vk);
-                        if (a < m1) {
-                            m2 = m1;
-                            m1 = a;
-                            i1 = k;
-                        } else if (a < m2) {
-                            m2 = a;
+                        if (a < M.m1) {
+                            M.m2 = M.m1;
+                            M.i2 = M.i1;
+                            M.m1 = a;
+                            M.i1 = k;
+                        } else if (a < M.m2) {
+                            M.m2 = a;
+                            M.i2 = k;
                         }
                     }
                 }
+                M = quad_combine(M, 1);
+                M = quad_combine(M, 2);
 #pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    if (k < d) {
+                for (int s = 0; s < SL; ++s) {
+                    const int k = q * SL + s;
+                    if (act && k < d) {
                         const int blk = o + k;
-                        const float mag = fmaxf((k == i1 ? m2 : m1) - bt[blk], 0.f);
-                        const float ln = (par ^ (v[k] < 0.f)) ? -mag : mag;
-                        L[(size_t)blk * z + r] = ln;
-                        E[col[k]] = v[k] + ln;
+                        const float mag = fmaxf((k == M.i1 ? M.m2 : M.m1) - bt[blk], 0.f);
+                        const float ln = (M.par ^ (v[s] < 0.f)) ? -mag : mag;
+                        L[lb + (size_t)r * d + k] = ln;
+                        E[col[s]] = v[s] + ln;
                     }
                 }
             }
@@ -172,17 +245,17 @@ __global__ __launch_bounds__(512) void k_oms_forward(DevCode C, OmsArgs A)
 }
 
 template <int DMAX, bool LDS>
-__global__ __launch_bounds__(512) void k_oms_backward(DevCode C, OmsArgs A)
+__global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
 {
+    constexpr int SL = DMAX / kQuad;
     const int f = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
     const int z = C.z, n = C.n, T = A.n_iter;
+    const int q = tid & (kQuad - 1), rq = tid / kQuad, nq = nthr / kQuad;
     const int lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
     const size_t ne = (size_t)C.n_blocks * z;
     OmsState S = oms_state(C, A, LDS, 16 * DMAX);
     float *Eb = S.E, *Lb = S.L;  // adjoints of E and L
-    const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
-    for (int i = tid; i < A.syn_bytes; i += nthr)
-        S.syn[i] = syn[i];
+    stage_common(C, A, S);
     for (int j = tid; j < n; j += nthr)
         Eb[j] = 0.f;
     for (size_t e = tid; e < ne; e += nthr)
@@ -192,7 +265,7 @@ __global__ __launch_bounds__(512) void k_oms_backward(DevCode C, OmsArgs A)
     const uint8_t *xb = A.xbits + (size_t)f * A.bit_bytes;
     const float g = A.dloss[f] / (float)n;
     for (int t = T - 1; t >= 0; --t) {
-        const float *bt = A.beta + (size_t)t * C.n_blocks;
+        const float *bt = S.beta + t * C.n_blocks;
         const float *tv = tape + (size_t)t * (ne + n);
         // the loss term of iteration t
         const float wt = (A.weights ? A.weights[t] : 1.f) * g;
@@ -203,92 +276,105 @@ __global__ __launch_bounds__(512) void k_oms_backward(DevCode C, OmsArgs A)
         __syncthreads();
         for (int b = C.mb - 1; b >= 0; --b) {
             const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
-            float acc[DMAX];
+            const size_t lb = (size_t)o * z;
+            float acc[SL];
 #pragma unroll
-            for (int k = 0; k < DMAX; ++k)
-                acc[k] = 0.f;
-            for (int r = tid; r < z; r += nthr) {
-                float v[DMAX], vb[DMAX], gk[DMAX];
-                int col[DMAX];
-                const int i = b * z + r;
-                int par = (S.syn[i >> 3] >> (i & 7)) & 1;
-                float m1 = INFINITY, m2 = INFINITY;
-                int i1 = 0, i2 = 0;
+            for (int s = 0; s < SL; ++s)
+                acc[s] = 0.f;
+            for (int r0 = 0; r0 < z; r0 += nq) {
+                const int r = r0 + rq;
+                const bool act = r < z;
+                float v[SL], vb[SL];
+                int col[SL];
+                RowMin M;
+                M.m1 = M.m2 = INFINITY;
+                M.i1 = M.i2 = DMAX;
+                M.par = 0;
+                if (act && q == 0) {
+                    const int i = b * z + r;
+                    M.par = (S.syn[i >> 3] >> (i & 7)) & 1;
+                }
 #pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    if (k < d) {
+                for (int s = 0; s < SL; ++s) {
+                    const int k = q * SL + s;
+                    v[s] = 0.f;
+                    col[s] = 0;
+                    if (act && k < d) {
                         const int blk = o + k;
-                        col[k] = ldc(C.colbase, blk) + rot(r, ldc(C.shift, blk), z);
-                        const float vk = tv[(size_t)blk * z + r];
-                        v[k] = vk;
-                        par ^= vk < 0.f;
+                        col[s] = ldc(C.colbase, blk) + rot(r, ldc(C.shift, blk), z);
+                        const float vk = tv[lb + (size_t)r * d + k];
+                        v[s] = vk;
+                        M.par ^= vk < 0.f;
                         const float a = fabsf(vk);
-                        if (a < m1) {
-                            m2 = m1;
-                            i2 = i1;
-                            m1 = a;
-                            i1 = k;
-                        } else if (a < m2) {
-                            m2 = a;
-                            i2 = k;
+                        if (a < M.m1) {
+                            M.m2 = M.m1;
+                            M.i2 = M.i1;
+                            M.m1 = a;
+                            M.i1 = k;
+                        } else if (a < M.m2) {
+                            M.m2 = a;
+                            M.i2 = k;
                         }
                     }
                 }
+                M = quad_combine(M, 1);
+                M = quad_combine(M, 2);
                 // adjoint of L_k (new) = its own adjoint + that of E_{j_k} (E = v + L)
                 float g_rest = 0.f, g_i1 = 0.f;
 #pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    gk[k] = 0.f;
-                    if (k < d) {
+                for (int s = 0; s < SL; ++s) {
+                    const int k = q * SL + s;
+                    vb[s] = 0.f;
+                    if (act && k < d) {
                         const int blk = o + k;
-                        const float eb = Eb[col[k]];
-                        const float a = Lb[(size_t)blk * z + r] + eb;
-                        const float sig = (par ^ (v[k] < 0.f)) ? -1.f : 1.f;
-                        const bool live = (k == i1 ? m2 : m1) - bt[blk] > 0.f;
+                        const float eb = Eb[col[s]];
+                        const float a = Lb[lb + (size_t)r * d + k] + eb;
+                        const float sig = (M.par ^ (v[s] < 0.f)) ? -1.f : 1.f;
+                        const bool live = (k == M.i1 ? M.m2 : M.m1) - bt[blk] > 0.f;
                         const float gg = live ? a * sig : 0.f;
-                        gk[k] = gg;
-                        acc[k] -= gg;
-                        vb[k] = eb;
-                        if (k == i1)
+                        acc[s] -= gg;
+                        vb[s] = eb;
+                        if (k == M.i1)
                             g_i1 = gg;
                         else
                             g_rest += gg;
                     }
                 }
-                // through the minima: every k != i1 read |v_i1|, k = i1 read |v_i2|
+                // every k != i1 read |v_i1|, k = i1 read |v_i2|: sum over the quad
+                g_rest += __shfl_xor(g_rest, 1, 64);
+                g_rest += __shfl_xor(g_rest, 2, 64);
+                g_i1 += __shfl_xor(g_i1, 1, 64);
+                g_i1 += __shfl_xor(g_i1, 2, 64);
 #pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    if (k < d) {
-                        const float sg = v[k] > 0.f ? 1.f : v[k] < 0.f ? -1.f : 0.f;
-                        if (k == i1)
-                            vb[k] += sg * g_rest;
-                        if (k == i2 && d > 1)
-                            vb[k] += sg * g_i1;
+                for (int s = 0; s < SL; ++s) {
+                    const int k = q * SL + s;
+                    if (act && k < d) {
+                        const float sg = v[s] > 0.f ? 1.f : v[s] < 0.f ? -1.f : 0.f;
+                        if (k == M.i1)
+                            vb[s] += sg * g_rest;
+                        if (k == M.i2)
+                            vb[s] += sg * g_i1;
+                        Eb[col[s]] = vb[s];
+                        Lb[lb + (size_t)r * d + k] = -vb[s];
                     }
                 }
-#pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    if (k < d) {
-                        Eb[col[k]] = vb[k];
-                        Lb[(size_t)(o + k) * z + r] = -vb[k];
-                    }
-                }
-                (void)gk;
             }
-            // offset gradients of this layer: fixed-order reduction over the workgroup
+            // offset gradients of this layer: fixed-order reduction over the
+            // workgroup (per edge slot: the quads of a wave, then the waves)
 #pragma unroll
-            for (int k = 0; k < DMAX; ++k) {
-                if (k < d) {
-                    const float s = wave_sum(acc[k]);
-                    if (lane == 0)
-                        S.red[w * DMAX + k] = s;
-                }
+            for (int s = 0; s < SL; ++s) {
+                float x = acc[s];
+#pragma unroll
+                for (int o2 = 32; o2 >= kQuad; o2 >>= 1)
+                    x += __shfl_xor(x, o2, 64);
+                if (lane < kQuad && lane * SL + s < d)
+                    S.red[w * DMAX + lane * SL + s] = x;
             }
             __syncthreads();
             if (tid < d) {
                 float s = 0.f;
-                for (int q = 0; q < nw; ++q)
-                    s += S.red[q * DMAX + tid];
+                for (int qq = 0; qq < nw; ++qq)
+                    s += S.red[qq * DMAX + tid];
                 A.dbeta_frames[((size_t)f * T + t) * C.n_blocks + o + tid] = s;
             }
             __syncthreads();
@@ -324,6 +410,11 @@ hipError_t fwd(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t
         }
         hipLaunchKernelGGL((k_oms_forward<DMAX, true>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
     } else {
+        if (P.lds_bytes > 65536) {
+            hipError_t e = allow_max_lds<k_oms_forward<DMAX, false>>();
+            if (e != hipSuccess)
+                return e;
+        }
         hipLaunchKernelGGL((k_oms_forward<DMAX, false>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
     }
     return hipGetLastError();
@@ -342,6 +433,11 @@ hipError_t bwd(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t
         }
         hipLaunchKernelGGL((k_oms_backward<DMAX, true>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
     } else {
+        if (P.lds_bytes > 65536) {
+            hipError_t e = allow_max_lds<k_oms_backward<DMAX, false>>();
+            if (e != hipSuccess)
+                return e;
+        }
         hipLaunchKernelGGL((k_oms_backward<DMAX, false>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
     }
     hipError_t e = hipGetLastError();
