@@ -80,7 +80,8 @@ enum {
     LDPC_HINT_LDS = 2,
     LDPC_HINT_PAIRS = 3,
     LDPC_HINT_SPLIT = 4,
-    LDPC_HINT_SPLIT_GLOBAL_L = 5
+    LDPC_HINT_SPLIT_GLOBAL_L = 5,
+    LDPC_HINT_LAYER_SYNC = 6
 };
 
 /* Build a code from a quasi-cyclic base matrix (Sec. 4.1).
@@ -140,15 +141,21 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
  * LDPC_KERNEL_SPLIT_GLOBAL_L  as LDPC_KERNEL_SPLIT with E in LDS and the CN
  *                      messages L in a global-memory slice per workgroup (codes
  *                      whose L does not fit in LDS beside E).
- * Automatic selection prefers them in the order SPLIT, SPLIT_GLOBAL_L, PAIRS,
- * LDS, GLOBAL, taking the first that applies. Also the workgroup size and the
- * dynamic LDS bytes per workgroup. Any output pointer may be NULL. */
+ * LDPC_KERNEL_LAYER_SYNC  one launch per layer over all frames, several
+ *                      workgroups per frame, E and L in global slices per frame
+ *                      (codes whose soft values do not fit in LDS, e.g. n = 2^20);
+ *                      the decode is a sequence of launches on the stream.
+ * Automatic selection prefers them in the order SPLIT, SPLIT_GLOBAL_L,
+ * LAYER_SYNC, PAIRS, LDS, GLOBAL, taking the first that applies. Also the
+ * workgroup size and the dynamic LDS bytes per workgroup. Any output pointer may
+ * be NULL. */
 enum {
     LDPC_KERNEL_GLOBAL = 0,
     LDPC_KERNEL_LDS = 1,
     LDPC_KERNEL_PAIRS = 2,
     LDPC_KERNEL_SPLIT = 3,
-    LDPC_KERNEL_SPLIT_GLOBAL_L = 4
+    LDPC_KERNEL_SPLIT_GLOBAL_L = 4,
+    LDPC_KERNEL_LAYER_SYNC = 5
 };
 int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int32_t *lds_bytes);
 

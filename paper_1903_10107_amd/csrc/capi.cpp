@@ -104,10 +104,12 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     // not fit, it moves to a global slice per workgroup (mb * Z * DMAX bytes)
     // and only E, the syndrome, the table and the vote words stay in LDS.
     P.split_global_l = false;
+    P.layer_sync = false;
     const bool split_hint = hint == LDPC_HINT_SPLIT || hint == LDPC_HINT_SPLIT_GLOBAL_L;
-    if ((hint == 0 || split_hint) && P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
-        (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM)) {
-        const int dmax = (h.min_deg == 6 && h.max_deg == 6) ? 6 : h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
+    const bool split_ok = P.pow2 && h.z >= 2 && h.offsets.empty() && h.max_deg <= 20 &&
+                          (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM);
+    const int dmax = (h.min_deg == 6 && h.max_deg == 6) ? 6 : h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
+    if ((hint == 0 || split_hint) && split_ok) {
         const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
         const size_t stride = (((size_t)h.mb * dh) | 1) * 4;
         const size_t l_sp = round_up((size_t)(h.z / 2) * stride, 16);
@@ -136,6 +138,23 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
         }
     }
     if (split_hint)
+        return false;
+    // Layer-synchronous (frames whose E does not fit in LDS beside the split
+    // kernel's tables): a global slice per frame holds E (plus the dummy block
+    // column) and L in the global-L chunk layout; the frame flags follow the
+    // slices in the workspace.
+    if ((hint == 0 || hint == LDPC_HINT_LAYER_SYNC) && split_ok) {
+        P.split_dmax = dmax;
+        P.layer_sync = true;
+        P.lds_state = false;
+        P.lds_bytes = 0;
+        P.threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
+        c->ws_l_off = round_up(((size_t)h.n + h.z) * esize, 256);
+        c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.mb * h.z * 4 * ((dh + 1) / 2), 256);
+        c->lane_tab_bytes = (size_t)h.mb * dh * 2 * 16;
+        return true;
+    }
+    if (hint == LDPC_HINT_LAYER_SYNC)
         return false;
     // Pairs (one lane per row pair): even Z. LDS: E at offset 0, L as
     // [pair][block][half] with an odd-dword stride per pair, the syndrome, two
@@ -201,10 +220,14 @@ bool is_persistent(const ldpc_schedule *sched) { return sched && sched->persiste
 
 // Queue slot (persistent) plus one state slice per frame, or per persistent
 // workgroup for the split kernel, whose slices belong to workgroups.
+size_t layer_sync_flag_bytes(int32_t n_frames) { return round_up((size_t)n_frames * 16, 256); }
+
 size_t workspace_need(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched)
 {
     if (is_persistent(sched))
         return kQueueBytes + code->ws_frame_bytes * (size_t)sched->persistent_workgroups;
+    if (code->plan.layer_sync)
+        return code->ws_frame_bytes * (size_t)n_frames + layer_sync_flag_bytes(n_frames);
     return code->ws_frame_bytes * (size_t)n_frames;
 }
 
@@ -224,7 +247,7 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
             return fail(LDPC_EINVAL, "ldpc_schedule: persistent_workgroups < 0");
         if (sched->order && sched->persistent_workgroups == 0)
             return fail(LDPC_EINVAL, "ldpc_schedule: order needs persistent_workgroups > 0");
-        if (sched->persistent_workgroups > 0 && !code->plan.split_dmax)
+        if (sched->persistent_workgroups > 0 && (!code->plan.split_dmax || code->plan.layer_sync))
             return fail(LDPC_EUNSUPPORTED, "ldpc_schedule: persistent workgroups need the split kernel family");
     }
     return LDPC_OK;
@@ -252,6 +275,8 @@ DecodeArgs make_args(const ldpc_code *code, const uint8_t *syndromes, const int8
         w += kQueueBytes;
     }
     A.ws = code->ws_frame_bytes ? w : nullptr;
+    if (code->plan.layer_sync)
+        A.mflags = reinterpret_cast<int *>(w + code->ws_frame_bytes * (size_t)n_frames);
     A.ws_frame_bytes = code->ws_frame_bytes;
     A.ws_l_off = code->ws_l_off;
     A.syn_bytes = (code->h.m + 7) / 8;
@@ -519,7 +544,8 @@ int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int
         return fail(LDPC_EINVAL, "ldpc_code_plan: code is NULL");
     const LaunchPlan &P = code->plan;
     if (kernel)
-        *kernel = P.split_dmax ? (P.split_global_l ? LDPC_KERNEL_SPLIT_GLOBAL_L : LDPC_KERNEL_SPLIT)
+        *kernel = P.layer_sync  ? LDPC_KERNEL_LAYER_SYNC
+                  : P.split_dmax ? (P.split_global_l ? LDPC_KERNEL_SPLIT_GLOBAL_L : LDPC_KERNEL_SPLIT)
                   : P.pairs    ? LDPC_KERNEL_PAIRS
                   : P.lds_state ? LDPC_KERNEL_LDS
                                 : LDPC_KERNEL_GLOBAL;
@@ -534,7 +560,7 @@ size_t ldpc_workspace_bytes(const ldpc_code *code, int32_t n_frames)
 {
     if (!code || n_frames < 0)
         return 0;
-    return code->ws_frame_bytes * (size_t)n_frames;
+    return workspace_need(code, n_frames, nullptr);
 }
 
 int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,

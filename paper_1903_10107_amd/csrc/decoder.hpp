@@ -32,6 +32,7 @@ struct DecodeArgs {
     int persistent_wgs;   // > 0: that many persistent workgroups pull frames from a queue
     int *queue;           // persistent: device counter (reset by k_queue_reset)
     const int32_t *order; // persistent: decode order, a permutation of the frames, or nullptr
+    int *mflags;          // layer-synchronous family: per frame {active, unsat, iterations, -}
 };
 
 struct LaunchPlan {
@@ -44,6 +45,7 @@ struct LaunchPlan {
     bool pow2;        // Z is a power of two
     int split_dmax;   // split kernel (two lanes per row pair) with this slot count, or 0
     bool split_global_l; // split kernel with L in a global slice per workgroup (E stays in LDS)
+    bool layer_sync;  // one launch per layer over all frames, E and L in global slices per frame
     size_t lds_bytes; // dynamic LDS per workgroup
 };
 
@@ -51,6 +53,7 @@ hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs
 hipError_t launch_decode_scalar(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+hipError_t launch_decode_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s);
 hipError_t launch_queue_reset(int *queue, hipStream_t s);
 hipError_t launch_reveal(int8_t *llr, int n, int n_frames, const int32_t *frame_ids, int k, const int32_t *positions,

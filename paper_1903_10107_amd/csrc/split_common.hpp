@@ -1,0 +1,311 @@
+// Row-pair machinery shared by the split decode kernels (two lanes per row
+// pair, both rows as the 16-bit halves of each register; arXiv:1903.10107,
+// Eqs. 1, 4, 8, 9, Alg. 1 and Alg. 2). See decode_split.hip for the layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace qkdldpc {
+
+typedef int8_t __attribute__((address_space(3))) lds_i8;
+typedef int16_t __attribute__((address_space(3))) lds_i16;
+template <typename ET>
+struct LdsPtr;
+template <>
+struct LdsPtr<int8_t> {
+    typedef lds_i8 *type;
+};
+template <>
+struct LdsPtr<int16_t> {
+    typedef lds_i16 *type;
+};
+
+// element at an absolute LDS byte address
+template <typename ET>
+__device__ __forceinline__ ET lds_ld(unsigned addr)
+{
+    return *(typename LdsPtr<ET>::type)(uintptr_t)addr;
+}
+template <typename ET>
+__device__ __forceinline__ void lds_st(unsigned addr, ET v)
+{
+    *(typename LdsPtr<ET>::type)(uintptr_t)addr = v;
+}
+
+// exchange a 32-bit value with the other lane of the pair (DPP quad_perm [1,0,3,2])
+__device__ __forceinline__ int swap_pair(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ s16x2 swap_pair(s16x2 x) { return __builtin_bit_cast(s16x2, swap_pair(__builtin_bit_cast(int, x))); }
+__device__ __forceinline__ u16x2 swap_pair(u16x2 x) { return __builtin_bit_cast(u16x2, swap_pair(__builtin_bit_cast(int, x))); }
+
+template <int DMIN, int DMAX>
+__host__ __device__ constexpr bool split_pad_slot(int i)
+{
+    // lane A's slot i is edge i; lane B's slot i is edge DMAX-1-i
+    return i >= DMIN || DMAX - 1 - i >= DMIN;
+}
+
+// Workgroup-wide OR of pred over three rotating LDS flag words: vote k writes
+// word k % 3, waits, reads it, and thread 0 clears word (k + 2) % 3, whose last
+// readers passed this barrier and whose next writers come after the next one.
+__device__ __forceinline__ int block_vote(int pred, int *flags, int &k)
+{
+    const int w = k;
+    if (pred)
+        flags[w] = 1;
+    __syncthreads();
+    const int any = flags[w];
+    if (threadIdx.x == 0)
+        flags[w == 0 ? 2 : w - 1] = 0;
+    k = w == 2 ? 0 : w + 1;
+    return any;
+}
+
+// E byte addresses of a row pair for its slot: a0 = ((r + shift) mod Z) + column
+// start, a1 = a0 with the Z/2 bit flipped (Z a power of two, column starts Z-aligned).
+__device__ __forceinline__ unsigned slot_addr(int4 te, int r, unsigned zm, unsigned esh)
+{
+    return ((((unsigned)r + (unsigned)te.x) & zm) << esh) | (unsigned)te.y;
+}
+
+// L slots of one lane for one row pair and layer.
+template <int DH, bool LG>
+struct LRef;
+
+// LDS, lane-interleaved: slot i of the lower half at p[2i], of the upper half at p[2DH + 2i]
+template <int DH>
+struct LRef<DH, false> {
+    int8_t *p;
+    __device__ __forceinline__ void load(s16x2 (&lk)[DH], bool) const
+    {
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            lk[i].x = (short)p[2 * i];
+            lk[i].y = (short)p[2 * DH + 2 * i];
+        }
+    }
+    __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
+    {
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            p[2 * i] = (int8_t)ln[i].x;
+            p[2 * DH + 2 * i] = (int8_t)ln[i].y;
+        }
+    }
+};
+
+// Global: ceil(DH/2) dwords (the chunk of one lane); dword k holds slot 2k
+// (lower half, upper half) in bytes 0 and 1 and slot 2k+1 in bytes 2 and 3
+// (zero past the last slot). zero: take L = 0 unread.
+template <int DH>
+struct LRef<DH, true> {
+    static constexpr int NW = (DH + 1) / 2;
+    static constexpr int BYTES = 4 * NW;
+    uint32_t *p;
+    __device__ __forceinline__ void load(s16x2 (&lk)[DH], bool zero) const
+    {
+        if (zero) {
+#pragma unroll
+            for (int i = 0; i < DH; ++i)
+                lk[i] = splat2(0);
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            s16x2 lo, hi;
+            unpack(p[k], lo, hi);
+            lk[2 * k] = lo;
+            if (2 * k + 1 < DH)
+                lk[2 * k + 1] = hi;
+        }
+    }
+    // bytes (b0, b1, b2, b3) -> slots (b0, b1) and (b2, b3): each byte moves to
+    // the top of a 16-bit half, then an arithmetic shift per half
+    static __device__ __forceinline__ void unpack(uint32_t w, s16x2 &lo, s16x2 &hi)
+    {
+        lo = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x010c000cu)) >> (short)8;
+        hi = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x030c020cu)) >> (short)8;
+    }
+    __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
+    {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const uint32_t a = __builtin_bit_cast(uint32_t, ln[2 * k]);
+            const uint32_t b = 2 * k + 1 < DH ? __builtin_bit_cast(uint32_t, ln[2 * k + 1]) : 0u;
+            p[k] = (a & 0xffu) | ((a >> 8) & 0xff00u) | ((b & 0xffu) << 16) | ((b << 8) & 0xff000000u);
+        }
+    }
+};
+
+template <int DH>
+struct SplitRow {
+    s16x2 e[DH], lk[DH];
+    unsigned a0[DH];
+    int pm[DH];
+};
+
+template <int DMIN, int DMAX, typename ET>
+__device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *__restrict__ tab, int r, unsigned zm,
+                                             unsigned hzb)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+        const int4 te = tab[2 * i];
+        const unsigned a0 = slot_addr(te, r, zm, esh);
+        R.a0[i] = a0;
+        R.pm[i] = te.z;
+        s16x2 ev;
+        ev.x = (short)lds_ld<ET>(a0);
+        ev.y = (short)lds_ld<ET>(a0 ^ hzb);
+        R.e[i] = ev;
+    }
+}
+
+template <int DMIN, int DMAX, typename ET, bool LG>
+__device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const LRef<DMAX / 2, LG> &Lr,
+                                           const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb,
+                                           bool first)
+{
+    split_load_e<DMIN, DMAX, ET>(R, tab, r, zm, hzb);
+    Lr.load(R.lk, first);
+}
+
+// XOR of the hard-decision sign bits of the row pair's slots held by this lane
+template <int DMIN, int DMAX>
+__device__ __forceinline__ s16x2 split_e_parity(const SplitRow<DMAX / 2> &R)
+{
+    constexpr int DH = DMAX / 2;
+    s16x2 own = splat2(0);
+#pragma unroll
+    for (int i = 0; i < DH; ++i)
+        own ^= split_pad_slot<DMIN, DMAX>(i) ? (R.e[i] & __builtin_bit_cast(s16x2, R.pm[i])) : R.e[i];
+    return own;
+}
+
+// E stores of the LDS kernels: both rows of the pair at absolute LDS addresses.
+template <typename ET>
+struct LdsESink {
+    unsigned hzb;  // the Z/2 bit of the byte address
+    __device__ __forceinline__ void operator()(unsigned a0, s16x2 o) const
+    {
+        lds_st<ET>(a0, (ET)o.x);
+        lds_st<ET>(a0 ^ hzb, (ET)o.y);
+    }
+};
+
+// Eq. 8, the check node (Eqs. 1, 4 by Alg. 1, or min-sum) and Eq. 9 under Alg. 2
+// for one lane's slots of a row pair; the new soft values go to es(a0, value),
+// the new messages to Lr.
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG, class ES>
+__device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DMAX / 2> &R,
+                                             const LRef<DMAX / 2, LG> &Lr, s16x2 syn, const ES &es)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr int ACC = AccLim<ET>::value;
+    const s16x2 em = splat2(C.e_max);
+    const u16x2 mm = usplat2(C.msg_max);
+    s16x2 v[DH];
+    u16x2 p[DH], X[DH], W[DH];
+    s16x2 own = splat2(0);
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+        // Eq. 8, saturated to the soft-value range
+        s16x2 vi = vmin2(vmax2(__builtin_elementwise_sub_sat(R.e[i], R.lk[i]), splat2(-ACC)), splat2(ACC));
+        u16x2 pi = as_u(vmin2(vmax2(vi, -vi), as_s(mm)));
+        if (split_pad_slot<DMIN, DMAX>(i)) {
+            const u16x2 mk = __builtin_bit_cast(u16x2, R.pm[i]);
+            vi = vi & __builtin_bit_cast(s16x2, R.pm[i]);
+            pi = (pi & mk) | (usplat2(kPad) & ~mk);
+        }
+        v[i] = vi;
+        own ^= vi;
+        p[i] = pi;
+    }
+    // sign product of Eq. 1 over the whole row, times the syndrome bit
+    const s16x2 par = syn ^ own ^ swap_pair(own);
+    u16x2 out[DH];
+    if constexpr (RULE == kRuleMinSum) {
+        u16x2 m1 = usplat2(0x7fff), m2 = usplat2(0x7fff);
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            m2 = umin2(m2, umax2(m1, p[i]));
+            m1 = umin2(m1, p[i]);
+        }
+        const u16x2 o1 = swap_pair(m1), o2 = swap_pair(m2);
+        m2 = umin2(umin2(m2, o2), umax2(m1, o1));
+        m1 = umin2(m1, o1);
+        const u16x2 diff = m2 - m1;
+#pragma unroll
+        for (int i = 0; i < DH; ++i)
+            out[i] = m2 - umin2(p[i] - m1, usplat2(1)) * diff;
+    } else {
+        X[0] = p[0];
+#pragma unroll
+        for (int i = 1; i < DH; ++i)
+            X[i] = tau2(X[i - 1], p[i]);
+        W[0] = swap_pair(X[DH - 1]);
+#pragma unroll
+        for (int k = 1; k < DH; ++k)
+            W[k] = tau2(W[k - 1], p[DH - k]);
+        out[0] = W[DH - 1];
+#pragma unroll
+        for (int i = 1; i < DH; ++i)
+            out[i] = tau2(X[i - 1], W[DH - 1 - i]);
+    }
+    s16x2 ln[DH];
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+        const s16x2 sg = (par ^ v[i]) >> (short)15;  // -1 in a half whose message is negative
+        const s16x2 mg = as_s(out[i]);
+        ln[i] = (mg ^ sg) - sg;
+        // Eq. 9 under Alg. 2: halves whose stored |E| is E_max keep E
+        const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln[i]), -em), em);
+        const s16x2 ae = vmax2(R.e[i], -R.e[i]);
+        const s16x2 frozen = vmin2(em - ae, splat2(1)) - splat2(1);
+        const s16x2 o = (frozen & R.e[i]) | (~frozen & ne);
+        es(R.a0[i], o);
+    }
+    Lr.store(ln);
+}
+
+// 1 when some check row of layers [b0, b1) owned by this lane pair fails
+template <int DMIN, int DMAX, typename ET>
+__device__ __forceinline__ int split_rows_unsat(const DevCode &C, const uint8_t *__restrict__ s_syn,
+                                                const int4 *__restrict__ s_tab, int h, int r, int b0, int b1)
+{
+    constexpr int DH = DMAX / 2;
+    constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
+    const int z = C.z, hz = z >> 1;
+    const unsigned zm = (unsigned)(z - 1), hzb = (unsigned)hz << esh;
+    s16x2 any = splat2(0);
+    for (int b = b0; b < b1; ++b) {
+        const int4 *tab = s_tab + b * DH * 2 + h;
+        s16x2 x[DH];
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            const int4 te = tab[2 * i];
+            const unsigned a0 = slot_addr(te, r, zm, esh);
+            x[i].x = (short)lds_ld<ET>(a0);
+            x[i].y = (short)lds_ld<ET>(a0 ^ hzb);
+            if (split_pad_slot<DMIN, DMAX>(i))
+                x[i] = x[i] & __builtin_bit_cast(s16x2, te.z);
+        }
+        s16x2 own = splat2(0);
+#pragma unroll
+        for (int i = 0; i < DH; ++i)
+            own ^= x[i];
+        any |= syn_pair(s_syn, b * z + r, b * z + r + hz) ^ own ^ swap_pair(own);
+    }
+    return (any.x | any.y) < 0;
+}
+
+
+} // namespace qkdldpc

@@ -87,6 +87,8 @@ hipError_t launch_queue_reset(int *queue, hipStream_t s)
 
 hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
+    if (P.layer_sync)
+        return launch_decode_multi(P, C, A, s);
     if (P.split_dmax)
         return launch_decode_split(P, C, A, s);
     if (P.pairs)

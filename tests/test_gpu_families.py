@@ -11,7 +11,7 @@ from paper_1903_10107_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-FAMILIES = ("global", "lds", "pairs", "split", "split_global_l")
+FAMILIES = ("global", "lds", "pairs", "split", "split_global_l", "layer_sync")
 
 
 def _say(msg):

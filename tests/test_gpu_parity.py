@@ -60,6 +60,13 @@ CASES = {
     "deg6_z2048_lds_rows_per_pair_2": (lambda: _rand_base(4, 8, 2048, 9), 2048, 4, 0.03, 20, {}, {}),
     "deg6_z4096_global_l_rows_per_pair_4": (lambda: _rand_base(6, 12, 4096, 8), 4096, 2, 0.04, 10, {}, {}),
     "n65536_deg20_global_l": (lambda: I.make_base(5, 32, 2048), 2048, 3, 0.02, 20, {}, {"short_frac": 0.33}),
+    "layer_sync_n32768": (lambda: I.make_base(5, 32, 1024), 1024, 5, 0.02, 40, {"kernel": "layer_sync"},
+                          {"short_frac": 0.3}),
+    "layer_sync_max_iter0": (lambda: I.make_base(5, 32, 64), 64, 6, 0.01, 0, {"kernel": "layer_sync"}, {}),
+    "layer_sync_minsum_acc16": (lambda: I.make_base(5, 32, 64), 64, 8, 0.01, 30,
+                                {"kernel": "layer_sync", "cn_rule": 2, "acc_bits": 16}, {}),
+    "layer_sync_deg6_ragged": (lambda: I.make_base(24, 48, 256), 256, 6, 0.04, 30, {"kernel": "layer_sync"},
+                               {"short_frac": 0.05, "punct_frac": 0.1}),
     "max_iter0": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 0, {}, {}),
     "zero_error": (lambda: I.make_base(5, 32, 32), 32, 8, 1e-9, 50, {}, {}),
     "row_deg_24": (lambda: _rand_base(2, 24, 64, 7, 2), 64, 8, 0.01, 30, {}, {}),
@@ -113,7 +120,7 @@ def test_cases_cover_every_kernel_family(B):
         if ckw.get("offsets") == "rand":
             ckw["offsets"] = np.zeros((1, int((mk() >= 0).sum())), np.int8)
         seen.add(B.Code(mk(), z, **ckw).plan()["kernel"])
-    assert seen == {"global", "lds", "pairs", "split", "split_global_l"}, seen
+    assert seen == {"global", "lds", "pairs", "split", "split_global_l", "layer_sync"}, seen
 
 
 def test_llr_minus_128_is_read_as_minus_127(B):

@@ -94,6 +94,13 @@ def test_schedule_argument_errors(B):
         B.ldpc_decode_batch_sched(odd, torch.from_numpy(fr2.syn).cuda(), torch.from_numpy(fr2.llr).cuda(), 2, 10,
                                   b2, c2, i2, persistent_workgroups=4)
     assert ei.value.code == B.LDPC_EUNSUPPORTED
+    ls = B.Code(I.make_base(5, 32, 64), 64, kernel="layer_sync")   # several launches per decode: no queue
+    fr3 = I.make_frames(I.Code(ls.base, 64), 2, 0.02, 1)
+    b3, c3, i3 = _outs(I.Code(ls.base, 64), 2)
+    with pytest.raises(B.LdpcError) as ei:
+        B.ldpc_decode_batch_sched(ls, torch.from_numpy(fr3.syn).cuda(), torch.from_numpy(fr3.llr).cuda(), 2, 10,
+                                  b3, c3, i3, persistent_workgroups=4)
+    assert ei.value.code == B.LDPC_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("wgs", [0, 256])
@@ -119,4 +126,32 @@ def test_graph_batch_replays_match_eager(B, wgs):
         assert np.array_equal(gb.cpu().numpy(), eager[0]), rep
         assert np.array_equal(gcv.cpu().numpy(), eager[1]), rep
         assert np.array_equal(gi.cpu().numpy(), eager[2]), rep
+    del batch
+
+
+def test_graph_of_a_layer_synchronous_decode_replays(B):
+    """The layer-synchronous family is a sequence of launches; captured as one
+    graph it replays to the eager result (with eager work between replays)."""
+    import torch
+    code = I.Code(I.make_base(5, 32, 256), 256)
+    fr = I.make_frames(code, 12, 0.02, 43, n_short=int(0.3 * code.n))
+    gc = B.Code(code.base, code.z, kernel="layer_sync")
+    syn, llr = torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda()
+    F = fr.n_frames
+    eb, ec, ei = _outs(code, F)
+    B.ldpc_decode_batch_sched(gc, syn, llr, F, 30, eb, ec, ei)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, 30)
+    assert np.array_equal(eb.cpu().numpy(), ref["bits"]) and np.array_equal(ei.cpu().numpy(), ref["iters"])
+    gb, gcv, gi = _outs(code, F)
+    batch = B.Batch(gc, syn, llr, F, 30, gb, gcv, gi)
+    for rep in range(3):
+        gb.zero_()
+        gi.fill_(-1)
+        scratch = torch.randn(1 << 14, device="cuda").sum()
+        batch.launch()
+        torch.cuda.synchronize()
+        assert float(scratch) == float(scratch)
+        assert np.array_equal(gb.cpu().numpy(), ref["bits"]), rep
+        assert np.array_equal(gi.cpu().numpy(), ref["iters"]), rep
     del batch
