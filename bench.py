@@ -50,13 +50,17 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1903_10107_amd", "csrc")
 
 
+# Sources the decode kernel of the headline workload (the split family) is compiled from.
+HEADLINE_KERNEL_SOURCES = ("decode_split.hip", "split_common.hpp", "kernels.hpp", "rcbp.hpp", "decoder.hpp",
+                           "qc_code.hpp")
+
+
 def kernel_source_hash() -> str:
-    """Hash of every kernel source and header the decode kernels are built from."""
+    """Hash of the sources the headline decode kernel is built from."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(name.encode())
-            h.update(open(os.path.join(CSRC, name), "rb").read())
+    for name in HEADLINE_KERNEL_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -345,6 +349,39 @@ def retry_figure(n_frames, extra=2048, step=512, max_rounds=12):
     return out
 
 
+def large_frames(steps, warmup):
+    """Frames of n = 1048576 (10x64 QC base, Z = 16384, 16-bit soft values), 32
+    frames, 80 iterations: the literal configuration at QBER 2% (every frame
+    runs all 80 iterations: a fixed amount of work) and the same code shortened
+    by a third (corrected-key throughput), on the layer-synchronous family,
+    whose launches are replayed as one HIP graph."""
+    import numpy as np
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+    from paper_1903_10107_amd import tune
+
+    wl = I.WORKLOADS["n1048576_q2"]
+    code = wl.code()
+    degs = [int((code.base[b] >= 0).sum()) for b in range(code.mb)]
+    out = {"workload": wl.name, "code": "10x64 QC base, Z=16384, column weight 3 (n=1048576)", "frames": wl.frames,
+           "max_iter": wl.max_iter, "soft_values": "int16"}
+    for name, frac in (("literal", 0.0), ("shortened_0.33", 0.33)):
+        fr = I.make_frames(code, wl.frames, wl.qber, 10107, n_short=int(frac * code.n))
+        # the decode is a few hundred launches: replayed as one HIP graph
+        run = tune.Runner(code.base, code.z, fr.syn, fr.llr, wl.max_iter, tune.Schedule(graph=True), None,
+                          wl.acc_bits)
+        ms = tune.time_ms(run, max(2, steps // 10), max(1, warmup // 2))
+        bits, conv, iters = run.outputs()
+        ok, und = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
+        tops = algorithmic_int_ops((code.z, degs), iters.sum()) / (ms / 1e3) / 1e12
+        out[name] = {"short_frac": frac, "ms_per_launch": round(ms, 3), "kernel": run.code.plan()["kernel"],
+                     "mean_iters": round(float(iters.mean()), 2), "fer": round(float(1 - ok.mean()), 4),
+                     "mbit_s": round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2),
+                     "frame_iterations_per_s": round(float(iters.sum()) / (ms / 1e3), 1),
+                     "alu_frac": round(tops / ALU_PEAK_TOPS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +399,7 @@ def main():
                     help="training steps of the learned-offset figure (0: skip)")
     ap.add_argument("--retry-frames", type=int, default=2048,
                     help="frames of the reveal-and-retry figure on the ragged batch (0: skip)")
+    ap.add_argument("--no-large", action="store_true", help="skip the n = 1048576 figure")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fer-sweep", default="",
@@ -505,6 +543,8 @@ def main():
         out["learned"] = learned(args.learned_steps, args.steps, args.warmup)
     if args.retry_frames:
         out["retry"] = retry_figure(args.retry_frames)
+    if not args.no_large:
+        out["large"] = large_frames(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

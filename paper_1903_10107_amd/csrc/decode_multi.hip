@@ -92,24 +92,27 @@ __global__ __launch_bounds__(256) void k_multi_stage_in(DevCode C, DecodeArgs A)
 }
 
 // Syndrome test of the current state: any failing row of an active frame sets
-// its unsat flag (one atomic per workgroup).
+// its unsat flag (one atomic per workgroup). Layers are tested one at a time and
+// a workgroup stops at the first layer with a failing row, or as soon as
+// another workgroup has flagged the frame: a frame that has not converged
+// almost always fails in layer 0, so the test costs a fraction of a pass.
 template <int DMIN, int DMAX, typename ET>
 __global__ __launch_bounds__(1024) void k_multi_check(DevCode C, DecodeArgs A)
 {
     constexpr int DH = DMAX / 2;
     const int f = blockIdx.y;
     int *fl = frame_flags(A, f);
-    if (!fl[0])
+    if (!fl[0] || __atomic_load_n(&fl[1], __ATOMIC_RELAXED))
         return;
     const int tid = threadIdx.x, h = tid & 1, z = C.z, hz = z >> 1;
     const int r = blockIdx.x * (blockDim.x >> 1) + (tid >> 1);
+    const bool act = r < hz;
     const unsigned zm = (unsigned)(z - 1);
     const ET *E = frame_e<ET>(A, f);
     const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
-    int fail = 0;
-    if (r < hz) {
-        s16x2 any = splat2(0);
-        for (int b = 0; b < C.mb; ++b) {
+    for (int b = 0; b < C.mb; ++b) {
+        int fail = 0;
+        if (act) {
             const int4 *tab = A.lane_tab + b * DH * 2 + h;
             s16x2 own = splat2(0);
 #pragma unroll
@@ -127,12 +130,15 @@ __global__ __launch_bounds__(1024) void k_multi_check(DevCode C, DecodeArgs A)
             s16x2 sp;
             sp.x = (short)(((syn[i0 >> 3] >> (i0 & 7)) & 1) ? -1 : 0);
             sp.y = (short)(((syn[i1 >> 3] >> (i1 & 7)) & 1) ? -1 : 0);
-            any |= sp ^ own ^ swap_pair(own);
+            const s16x2 pe = sp ^ own ^ swap_pair(own);
+            fail = (pe.x | pe.y) < 0;
         }
-        fail = (any.x | any.y) < 0;
+        if (__syncthreads_or(fail)) {
+            if (tid == 0)
+                atomicOr(&fl[1], 1);
+            return;
+        }
     }
-    if (__syncthreads_or(fail) && tid == 0)
-        atomicOr(&fl[1], 1);
 }
 
 // Retire frames: converged at iteration t (no failing row), or out of iterations.
