@@ -67,7 +67,10 @@ typedef struct {
     const int8_t *offsets;  /* HOST pointer or NULL: [offset_iters][n_blocks] magnitude offsets,
                                subtracted from every CN message magnitude at iteration t using
                                row min(t-1, offset_iters-1), result clamped to [0, msg_max];
-                               copied at create. NULL = no offsets (the paper's decoder). */
+                               copied at create. NULL = no offsets (the paper's decoder).
+                               Served by the split family with L in LDS and by the pairs, lds
+                               and global families; split_global_l and layer_sync refuse them
+                               (LDPC_EUNSUPPORTED when forced). */
     int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
     int32_t kernel_hint;    /* 0: pick the kernel family automatically; LDPC_HINT_*: use that
                                family, or fail with LDPC_EUNSUPPORTED when it does not apply

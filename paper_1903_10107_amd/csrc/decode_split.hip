@@ -60,10 +60,18 @@ constexpr int split_pd() { return DMAX <= 8 ? 3 : 2; }
 
 // Decode frame f with one workgroup (the LDS table must already be staged).
 // LG: L in the global slice Lg of this workgroup, else in LDS.
-template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG, bool OFF>
 __device__ __forceinline__ void split_decode_frame(const DevCode &C, const DecodeArgs &A, const SplitLds<ET> &M,
                                                    uint8_t *Lg, int f)
 {
+    static_assert(!(LG && OFF), "offset tables are served with L in LDS");
+    // the offset table's row of iteration t (OFF): min(t - 1, offset_iters - 1)
+    auto off_row = [&](int t) -> const int32_t * {
+        if constexpr (OFF)
+            return C.offsets + (size_t)(t - 1 < C.offset_iters - 1 ? t - 1 : C.offset_iters - 1) * C.n_blocks;
+        else
+            return nullptr;
+    };
     constexpr int DH = DMAX / 2;
     constexpr int RPL = split_rpl<DMAX>();
     constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
@@ -129,7 +137,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                         syn0[k] = splat2(0);
                         if (r < hz) {
                             syn0[k] = syn_pair(s_syn, r, r + hz);
-                            split_load<DMIN, DMAX, ET, LG>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1);
+                            split_load<DMIN, DMAX, ET, LG, OFF>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1,
+                                                                off_row(t));
                         }
                     }
                     if (t >= 2) {
@@ -153,7 +162,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     for (int k = 0; k < RPL; ++k) {
                         const int r = lp + k * np;
                         if (r < hz)
-                            split_finish<DMIN, DMAX, ET, RULE, LG>(C, R[k], lref(0, r), syn0[k], es);
+                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R[k], lref(0, r), syn0[k], es);
                     }
                     __syncthreads();
                 }
@@ -164,9 +173,10 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                         if (r < hz) {
                             SplitRow<DH> R;
                             const auto Lr = lref(b, r);
-                            split_load<DMIN, DMAX, ET, LG>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1);
-                            split_finish<DMIN, DMAX, ET, RULE, LG>(C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz),
-                                                                   es);
+                            split_load<DMIN, DMAX, ET, LG, OFF>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1,
+                                                                off_row(t));
+                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(
+                                C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz), es);
                         }
                     }
                     __syncthreads();
@@ -277,8 +287,10 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                 for (int r = lp; r < hz; r += np) {
                     SplitRow<DH> R;
                     const auto Lr = lref(b, r);
-                    split_load<DMIN, DMAX, ET, LG>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1);
-                    split_finish<DMIN, DMAX, ET, RULE, LG>(C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz), es);
+                    split_load<DMIN, DMAX, ET, LG, OFF>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1,
+                                                        off_row(t));
+                    split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R, Lr,
+                                                                syn_pair(s_syn, b * z + r, b * z + r + hz), es);
                 }
                 __syncthreads();
             }
@@ -373,7 +385,7 @@ __device__ __forceinline__ uint8_t *split_l_slice(const DecodeArgs &A)
 }
 
 // One workgroup per frame (grid = frames).
-template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG, bool OFF>
 __global__ __launch_bounds__(1024) void k_decode_frame_split(DevCode C, DecodeArgs A)
 {
     SplitLds<ET> M;
@@ -387,14 +399,14 @@ __global__ __launch_bounds__(1024) void k_decode_frame_split(DevCode C, DecodeAr
         return;
     }
     split_stage_table<ET>(C, A, M, DMAX / 2);
-    split_decode_frame<DMIN, DMAX, ET, RULE, LG>(C, A, M, split_l_slice<LG>(A), f);
+    split_decode_frame<DMIN, DMAX, ET, RULE, LG, OFF>(C, A, M, split_l_slice<LG>(A), f);
 }
 
 // Persistent workgroups: each one takes the next position of a device queue
 // (atomic counter, reset to 0 by k_queue_reset before the launch), decodes
 // frame order[position] (or position), and stops once the queue is past the
 // last frame, which every wave of every workgroup reaches.
-template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG, bool OFF>
 __global__ __launch_bounds__(1024) void k_decode_split_persistent(DevCode C, DecodeArgs A)
 {
     SplitLds<ET> M;
@@ -412,21 +424,21 @@ __global__ __launch_bounds__(1024) void k_decode_split_persistent(DevCode C, Dec
             break;
         const int f = A.order ? A.order[q] : q;
         if ((unsigned)f < (unsigned)A.n_frames)
-            split_decode_frame<DMIN, DMAX, ET, RULE, LG>(C, A, M, Lg, f);
+            split_decode_frame<DMIN, DMAX, ET, RULE, LG, OFF>(C, A, M, Lg, f);
     }
 }
 
 namespace {
 
-template <int DMIN, int DMAX, typename ET, int RULE, bool LG>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG, bool OFF>
 hipError_t launch_one_split(const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
 {
     const bool persistent = A.persistent_wgs > 0;
-    auto kern = persistent ? k_decode_split_persistent<DMIN, DMAX, ET, RULE, LG>
-                           : k_decode_frame_split<DMIN, DMAX, ET, RULE, LG>;
+    auto kern = persistent ? k_decode_split_persistent<DMIN, DMAX, ET, RULE, LG, OFF>
+                           : k_decode_frame_split<DMIN, DMAX, ET, RULE, LG, OFF>;
     if (lds > 65536) {
-        hipError_t e = persistent ? allow_max_lds<k_decode_split_persistent<DMIN, DMAX, ET, RULE, LG>>()
-                                  : allow_max_lds<k_decode_frame_split<DMIN, DMAX, ET, RULE, LG>>();
+        hipError_t e = persistent ? allow_max_lds<k_decode_split_persistent<DMIN, DMAX, ET, RULE, LG, OFF>>()
+                                  : allow_max_lds<k_decode_frame_split<DMIN, DMAX, ET, RULE, LG, OFF>>();
         if (e != hipSuccess)
             return e;
     }
@@ -439,27 +451,27 @@ hipError_t launch_one_split(const DevCode &C, const DecodeArgs &A, int threads, 
     return hipGetLastError();
 }
 
-template <int DMIN, int DMAX, typename ET, bool LG>
+template <int DMIN, int DMAX, typename ET, bool LG, bool OFF>
 hipError_t launch_rule_split(int rule, const DevCode &C, const DecodeArgs &A, int threads, size_t lds,
                              hipStream_t s)
 {
     if (rule == LDPC_RULE_MINSUM)
-        return launch_one_split<DMIN, DMAX, ET, kRuleMinSum, LG>(C, A, threads, lds, s);
-    return launch_one_split<DMIN, DMAX, ET, kRuleRcbpFB, LG>(C, A, threads, lds, s);
+        return launch_one_split<DMIN, DMAX, ET, kRuleMinSum, LG, OFF>(C, A, threads, lds, s);
+    return launch_one_split<DMIN, DMAX, ET, kRuleRcbpFB, LG, OFF>(C, A, threads, lds, s);
 }
 
-template <typename ET, bool LG>
+template <typename ET, bool LG, bool OFF>
 hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
     switch (P.split_dmax) {
     case 6:
-        return launch_rule_split<6, 6, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+        return launch_rule_split<6, 6, ET, LG, OFF>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
     case 8:
-        return P.min_deg >= 6 ? launch_rule_split<6, 8, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
-                              : launch_rule_split<2, 8, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+        return P.min_deg >= 6 ? launch_rule_split<6, 8, ET, LG, OFF>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
+                              : launch_rule_split<2, 8, ET, LG, OFF>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
     default:
-        return P.min_deg >= 19 ? launch_rule_split<19, 20, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
-                               : launch_rule_split<2, 20, ET, LG>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
+        return P.min_deg >= 19 ? launch_rule_split<19, 20, ET, LG, OFF>(P.cn_rule, C, A, P.threads, P.lds_bytes, s)
+                               : launch_rule_split<2, 20, ET, LG, OFF>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
     }
 }
 
@@ -468,8 +480,13 @@ hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs 
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
     if (P.split_global_l)
-        return P.acc_bits == 16 ? launch_split<int16_t, true>(P, C, A, s) : launch_split<int8_t, true>(P, C, A, s);
-    return P.acc_bits == 16 ? launch_split<int16_t, false>(P, C, A, s) : launch_split<int8_t, false>(P, C, A, s);
+        return P.acc_bits == 16 ? launch_split<int16_t, true, false>(P, C, A, s)
+                                : launch_split<int8_t, true, false>(P, C, A, s);
+    if (C.offsets)
+        return P.acc_bits == 16 ? launch_split<int16_t, false, true>(P, C, A, s)
+                                : launch_split<int8_t, false, true>(P, C, A, s);
+    return P.acc_bits == 16 ? launch_split<int16_t, false, false>(P, C, A, s)
+                            : launch_split<int8_t, false, false>(P, C, A, s);
 }
 
 } // namespace qkdldpc

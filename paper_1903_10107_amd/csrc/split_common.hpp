@@ -148,11 +148,14 @@ struct SplitRow {
     s16x2 e[DH], lk[DH];
     unsigned a0[DH];
     int pm[DH];
+    unsigned off[(DH + 1) / 2];  // magnitude offsets of the slots' blocks, 16 bits each (offset tables only)
 };
 
-template <int DMIN, int DMAX, typename ET>
+// off_row: the offset table's row of the current iteration (OFF only); padding
+// slots (block -1) take offset 0.
+template <int DMIN, int DMAX, typename ET, bool OFF = false>
 __device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *__restrict__ tab, int r, unsigned zm,
-                                             unsigned hzb)
+                                             unsigned hzb, const int32_t *__restrict__ off_row = nullptr)
 {
     constexpr int DH = DMAX / 2;
     constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
@@ -166,15 +169,19 @@ __device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *
         ev.x = (short)lds_ld<ET>(a0);
         ev.y = (short)lds_ld<ET>(a0 ^ hzb);
         R.e[i] = ev;
+        if constexpr (OFF) {
+            const unsigned o = (unsigned)(te.w >= 0 ? off_row[te.w] : 0) & 0xffffu;
+            R.off[i / 2] = i % 2 ? R.off[i / 2] | (o << 16) : o;
+        }
     }
 }
 
-template <int DMIN, int DMAX, typename ET, bool LG>
+template <int DMIN, int DMAX, typename ET, bool LG, bool OFF = false>
 __device__ __forceinline__ void split_load(SplitRow<DMAX / 2> &R, const LRef<DMAX / 2, LG> &Lr,
                                            const int4 *__restrict__ tab, int r, unsigned zm, unsigned hzb,
-                                           bool first)
+                                           bool first, const int32_t *__restrict__ off_row = nullptr)
 {
-    split_load_e<DMIN, DMAX, ET>(R, tab, r, zm, hzb);
+    split_load_e<DMIN, DMAX, ET, OFF>(R, tab, r, zm, hzb, off_row);
     Lr.load(R.lk, first);
 }
 
@@ -204,7 +211,7 @@ struct LdsESink {
 // Eq. 8, the check node (Eqs. 1, 4 by Alg. 1, or min-sum) and Eq. 9 under Alg. 2
 // for one lane's slots of a row pair; the new soft values go to es(a0, value),
 // the new messages to Lr.
-template <int DMIN, int DMAX, typename ET, int RULE, bool LG, class ES>
+template <int DMIN, int DMAX, typename ET, int RULE, bool LG, bool OFF = false, class ES>
 __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DMAX / 2> &R,
                                              const LRef<DMAX / 2, LG> &Lr, s16x2 syn, const ES &es)
 {
@@ -259,6 +266,15 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
 #pragma unroll
         for (int i = 1; i < DH; ++i)
             out[i] = tau2(X[i - 1], W[DH - 1 - i]);
+    }
+    if constexpr (OFF) {
+        // offset table: magnitude = clamp(mag - offset, 0, MSG_max) (both halves share the block)
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            const unsigned sel = i % 2 ? 0x03020302u : 0x01000100u;  // splat the slot's 16-bit half
+            const s16x2 oi = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(R.off[i / 2], R.off[i / 2], sel));
+            out[i] = as_u(vmin2(vmax2(as_s(out[i]) - oi, splat2(0)), as_s(mm)));
+        }
     }
     s16x2 ln[DH];
 #pragma unroll

@@ -62,6 +62,31 @@ def test_forced_family_matches_oracle(B, name, family):
         assert np.array_equal(got[k], ref[k]), (name, family, k)
 
 
+@pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("name", ["n1024", "n6144_deg6", "n3840_deg10_w2", "n2048_deg4_w2"])
+def test_offset_tables_on_every_family(B, name, family):
+    """Per-iteration offsets (signed, fewer rows than iterations): the families
+    that keep L in LDS or in a per-frame global slice serve them; the streamed-L
+    and layer-synchronous families refuse them."""
+    mb, nb, z, F, q, short, cw = CODES[name]
+    code = I.Code(I.make_base(mb, nb, z, cw), z)
+    fr = I.make_frames(code, F, q, 4321 + z, n_short=int(short * code.n))
+    off = np.random.default_rng(z).integers(-3, 8, size=(4, code.n_blocks)).astype(np.int8)
+    try:
+        gc = B.Code(code.base, z, kernel=family, cn_rule=2, offsets=off)
+    except B.LdpcError as e:
+        assert e.code == B.LDPC_EUNSUPPORTED
+        assert family not in ("global", "split") or name != "n1024", e
+        pytest.skip(f"{family} does not serve offsets on {name}: {e}")
+    assert family not in ("split_global_l", "layer_sync")
+    assert gc.plan()["kernel"] == family
+    _say(f"[gpu family offsets] {name} {family} {gc.plan()}")
+    got = B.decode(gc, fr.syn, fr.llr, 40, want_state=True)
+    ref = O.decode(code.base, z, fr.syn, fr.llr, 40, want_state=True, cn_rule=O.RULE_MINSUM, offsets=off)
+    for k in ("bits", "conv", "iters", "L", "E"):
+        assert np.array_equal(got[k], ref[k]), (name, family, k)
+
+
 def test_global_family_applies_to_every_code(B):
     for name, (mb, nb, z, *_rest, cw) in CODES.items():
         assert B.Code(I.make_base(mb, nb, z, cw), z, kernel="global").plan()["kernel"] == "global"

@@ -53,6 +53,11 @@ CASES = {
     "rule_minsum": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2}, {}),
     "minsum_offsets": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2, "offsets": "rand"}, {}),
     "rcbp_offsets": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"offsets": "rand"}, {}),
+    "minsum_signed_offsets_acc16": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30,
+                                    {"cn_rule": 2, "offsets": "rand_signed", "acc_bits": 16}, {}),
+    "eq7_offsets": (lambda: I.make_base(5, 32, 32), 32, 8, 0.02, 30, {"cn_rule": 1, "offsets": "rand_signed"}, {}),
+    "deg6_offsets": (lambda: I.make_base(12, 24, 256), 256, 6, 0.04, 30, {"offsets": "rand_signed"},
+                     {"short_frac": 0.1}),
     "deg6_n98304_global_state": (lambda: I.make_base(24, 48, 2048), 2048, 2, 0.04, 8, {"kernel": "global"},
                                  {"short_frac": 0.1, "punct_frac": 0.1}),
     "deg6_n98304_global_l": (lambda: I.make_base(24, 48, 2048), 2048, 3, 0.04, 12, {},
@@ -98,9 +103,11 @@ def test_parity_small(B, name):
     code, fr = _frames(base, z, F, q, fkw, seed=zlib.crc32(name.encode()) & 0xFFFF)
     ckw = dict(ckw)
     okw = {}
-    if ckw.get("offsets") == "rand":
+    if ckw.get("offsets") in ("rand", "rand_signed"):
+        # three iterations' rows; later iterations reuse the last one
         rng = np.random.default_rng(1)
-        ckw["offsets"] = rng.integers(0, 4, size=(3, code.n_blocks)).astype(np.int8)
+        lo, hi = (0, 4) if ckw["offsets"] == "rand" else (-4, 8)
+        ckw["offsets"] = rng.integers(lo, hi, size=(3, code.n_blocks)).astype(np.int8)
     if "offsets" in ckw:
         okw["offsets"] = ckw["offsets"]
     for k in ("acc_bits", "e_max", "msg_max", "cn_rule"):
@@ -117,7 +124,7 @@ def test_cases_cover_every_kernel_family(B):
     seen = set()
     for name, (mk, z, F, q, it, ckw, fkw) in CASES.items():
         ckw = dict(ckw)
-        if ckw.get("offsets") == "rand":
+        if ckw.get("offsets") in ("rand", "rand_signed"):
             ckw["offsets"] = np.zeros((1, int((mk() >= 0).sum())), np.int8)
         seen.add(B.Code(mk(), z, **ckw).plan()["kernel"])
     assert seen == {"global", "lds", "pairs", "split", "split_global_l", "layer_sync"}, seen

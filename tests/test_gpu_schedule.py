@@ -62,6 +62,25 @@ def test_persistent_schedule_matches_oracle(B, wgs, ordered):
     assert np.array_equal(iters.cpu().numpy(), ref["iters"])
 
 
+def test_persistent_schedule_with_offset_table(B):
+    import torch
+    code = I.Code(I.make_base(5, 32, 256), 256)
+    fr = I.make_frames(code, 24, 0.02, 8, n_short=int(0.2 * code.n))
+    off = np.random.default_rng(3).integers(-2, 6, size=(5, code.n_blocks)).astype(np.int8)
+    gc = B.Code(code.base, code.z, cn_rule=B.LDPC_RULE_MINSUM, offsets=off)
+    assert gc.plan()["kernel"] == "split"
+    _say(f"[gpu schedule] persistent with offsets {gc.plan()}")
+    F = fr.n_frames
+    bits, conv, iters = _outs(code, F)
+    B.ldpc_decode_batch_sched(gc, torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda(), F, 40,
+                              bits, conv, iters, persistent_workgroups=5)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, 40, cn_rule=O.RULE_MINSUM, offsets=off)
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+    assert np.array_equal(conv.cpu().numpy(), ref["conv"])
+    assert np.array_equal(iters.cpu().numpy(), ref["iters"])
+
+
 def test_order_with_out_of_range_entries_skips_them(B):
     import torch
     code, fr, gc, dev = _setup(B, F=12)
