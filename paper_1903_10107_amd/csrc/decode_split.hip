@@ -112,8 +112,9 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     int conv, iters = 0;
     const int lp = tid >> 1, np = nthr >> 1;
     // global L on this path: every lane pair owns RPL row pairs, and there are
-    // more layers than the prefetch distance
-    if (LG ? hz == RPL * np && C.mb > split_pd<DMAX>() : hz <= RPL * np) {
+    // more layers than the prefetch distance; L in LDS: at most 32 layers (the
+    // syndrome bits of a lane's rows fit two registers)
+    if (LG ? hz == RPL * np && C.mb > split_pd<DMAX>() : hz <= RPL * np && C.mb <= 32) {
         // every row pair has a lane pair: the check is folded into layer 0
         auto unsat_range = [&](int b0, int b1) {
             int u = 0;
@@ -127,6 +128,27 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
         };
         conv = !block_vote(unsat_range(0, C.mb), flags, vk);
         if constexpr (!LG) {
+            // Each lane keeps its row pairs' syndrome bits in registers (this path
+            // takes at most 32 layers): word b / 16, bit b % 16 for row b*Z + r and
+            // bit 16 + b % 16 for row b*Z + r + Z/2; layer b's pair (the sign bits
+            // of two 16-bit halves) is then (word << (15 - b % 16)) & 0x80008000.
+            unsigned synm[RPL][2];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int r = lp + k * np;
+                synm[k][0] = synm[k][1] = 0;
+                if (r < hz)
+                    for (int b = 0; b < C.mb; ++b) {
+                        const int i0 = b * z + r, i1 = i0 + hz;
+                        const unsigned bits = (unsigned)((s_syn[i0 >> 3] >> (i0 & 7)) & 1) << (b & 15) |
+                                              (unsigned)((s_syn[i1 >> 3] >> (i1 & 7)) & 1) << (16 + (b & 15));
+                        synm[k][b >> 4] |= bits;
+                    }
+            }
+            auto syn_of = [&](int k, int b) {
+                const unsigned w = b < 16 ? synm[k][0] : synm[k][1];
+                return __builtin_bit_cast(s16x2, (w << (15 - (b & 15))) & 0x80008000u);
+            };
             for (int t = 1; t <= A.max_iter && !conv; ++t) {
                 {
                     SplitRow<DH> R[RPL];
@@ -136,7 +158,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                         const int r = lp + k * np;
                         syn0[k] = splat2(0);
                         if (r < hz) {
-                            syn0[k] = syn_pair(s_syn, r, r + hz);
+                            syn0[k] = syn_of(k, 0);
                             split_load<DMIN, DMAX, ET, LG, OFF>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1,
                                                                 off_row(t));
                         }
@@ -175,8 +197,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                             const auto Lr = lref(b, r);
                             split_load<DMIN, DMAX, ET, LG, OFF>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1,
                                                                 off_row(t));
-                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(
-                                C, R, Lr, syn_pair(s_syn, b * z + r, b * z + r + hz), es);
+                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R, Lr, syn_of(k, b), es);
                         }
                     }
                     __syncthreads();

@@ -36,6 +36,13 @@ __device__ __forceinline__ void lds_st(unsigned addr, ET v)
     *(typename LdsPtr<ET>::type)(uintptr_t)addr = v;
 }
 
+// two sign-extended values as the halves of one register: the low 16 bits of
+// lo and of hi (one v_perm; the loads stay sign-extending byte loads)
+__device__ __forceinline__ s16x2 pack_halves(int lo, int hi)
+{
+    return __builtin_bit_cast(s16x2, __builtin_amdgcn_perm((unsigned)hi, (unsigned)lo, 0x05040100u));
+}
+
 // exchange a 32-bit value with the other lane of the pair (DPP quad_perm [1,0,3,2])
 __device__ __forceinline__ int swap_pair(int x)
 {
@@ -71,7 +78,9 @@ __device__ __forceinline__ int block_vote(int pred, int *flags, int &k)
 // start, a1 = a0 with the Z/2 bit flipped (Z a power of two, column starts Z-aligned).
 __device__ __forceinline__ unsigned slot_addr(int4 te, int r, unsigned zm, unsigned esh)
 {
-    return ((((unsigned)r + (unsigned)te.x) & zm) << esh) | (unsigned)te.y;
+    // (t & mask) | start in one bitop3 (truth table 0xEA); the second row's
+    // address is then one XOR
+    return __builtin_amdgcn_bitop3_b32(((unsigned)r + (unsigned)te.x) << esh, zm << esh, (unsigned)te.y, 0xEA);
 }
 
 // L slots of one lane for one row pair and layer.
@@ -86,8 +95,7 @@ struct LRef<DH, false> {
     {
 #pragma unroll
         for (int i = 0; i < DH; ++i) {
-            lk[i].x = (short)p[2 * i];
-            lk[i].y = (short)p[2 * DH + 2 * i];
+            lk[i] = pack_halves(p[2 * i], p[2 * DH + 2 * i]);
         }
     }
     __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
@@ -165,10 +173,7 @@ __device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *
         const unsigned a0 = slot_addr(te, r, zm, esh);
         R.a0[i] = a0;
         R.pm[i] = te.z;
-        s16x2 ev;
-        ev.x = (short)lds_ld<ET>(a0);
-        ev.y = (short)lds_ld<ET>(a0 ^ hzb);
-        R.e[i] = ev;
+        R.e[i] = pack_halves(lds_ld<ET>(a0), lds_ld<ET>(a0 ^ hzb));
         if constexpr (OFF) {
             const unsigned o = (unsigned)(te.w >= 0 ? off_row[te.w] : 0) & 0xffffu;
             R.off[i / 2] = i % 2 ? R.off[i / 2] | (o << 16) : o;
@@ -217,7 +222,7 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
 {
     constexpr int DH = DMAX / 2;
     constexpr int ACC = AccLim<ET>::value;
-    const s16x2 em = splat2(C.e_max);
+    const s16x2 em = splat2(C.e_max), em1 = splat2(C.e_max - 1);
     const u16x2 mm = usplat2(C.msg_max);
     s16x2 v[DH];
     u16x2 p[DH], X[DH], W[DH];
@@ -283,10 +288,20 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
         const s16x2 mg = as_s(out[i]);
         ln[i] = (mg ^ sg) - sg;
         // Eq. 9 under Alg. 2: halves whose stored |E| is E_max keep E
-        const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln[i]), -em), em);
-        const s16x2 ae = vmax2(R.e[i], -R.e[i]);
-        const s16x2 frozen = vmin2(em - ae, splat2(1)) - splat2(1);
-        const s16x2 o = (frozen & R.e[i]) | (~frozen & ne);
+        s16x2 o;
+        if constexpr (sizeof(ET) == 1) {
+            // g = E - clamp(E, +-(E_max - 1)) is +-1 exactly where |E| = E_max and 0
+            // elsewhere; 511 g (odd, so one multiply-add) drives the sum past
+            // +-E_max there, and the clamp returns E itself (no 16-bit overflow:
+            // |v + ln + 511 g| <= 127 + 127 + 511)
+            const s16x2 g = R.e[i] - vmin2(vmax2(R.e[i], -em1), em1);
+            o = vmin2(vmax2(v[i] + (g * splat2(511) + ln[i]), -em), em);
+        } else {
+            const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln[i]), -em), em);
+            const s16x2 ae = vmax2(R.e[i], -R.e[i]);
+            const s16x2 frozen = vmin2(em - ae, splat2(1)) - splat2(1);
+            o = (frozen & R.e[i]) | (~frozen & ne);
+        }
         es(R.a0[i], o);
     }
     Lr.store(ln);
@@ -309,8 +324,7 @@ __device__ __forceinline__ int split_rows_unsat(const DevCode &C, const uint8_t 
         for (int i = 0; i < DH; ++i) {
             const int4 te = tab[2 * i];
             const unsigned a0 = slot_addr(te, r, zm, esh);
-            x[i].x = (short)lds_ld<ET>(a0);
-            x[i].y = (short)lds_ld<ET>(a0 ^ hzb);
+            x[i] = pack_halves(lds_ld<ET>(a0), lds_ld<ET>(a0 ^ hzb));
             if (split_pad_slot<DMIN, DMAX>(i))
                 x[i] = x[i] & __builtin_bit_cast(s16x2, te.z);
         }
