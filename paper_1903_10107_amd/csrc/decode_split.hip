@@ -149,27 +149,35 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                 const unsigned w = b < 16 ? synm[k][0] : synm[k][1];
                 return __builtin_bit_cast(s16x2, (w << (15 - (b & 15))) & 0x80008000u);
             };
+            // Each layer step reads its slot addresses and L (private to the lane,
+            // written by it one iteration earlier) before the barrier that orders
+            // the previous step's E writes, so that after it only E is waited for.
+            auto prepare = [&](SplitRow<DH> (&R)[RPL], int t, int b) {
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int r = lp + k * np;
+                    if (r < hz) {
+                        split_addr<DMIN, DMAX, ET, OFF>(R[k], s_tab + b * DH * 2 + h, r, zm, off_row(t));
+                        lref(b, r).load(R[k].lk, t == 1);
+                    }
+                }
+            };
             for (int t = 1; t <= A.max_iter && !conv; ++t) {
                 {
                     SplitRow<DH> R[RPL];
-                    s16x2 syn0[RPL];
+                    prepare(R, t, 0);
+                    __syncthreads();
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) {
-                        const int r = lp + k * np;
-                        syn0[k] = splat2(0);
-                        if (r < hz) {
-                            syn0[k] = syn_of(k, 0);
-                            split_load<DMIN, DMAX, ET, LG, OFF>(R[k], lref(0, r), s_tab + h, r, zm, hzb, t == 1,
-                                                                off_row(t));
-                        }
-                    }
+                    for (int k = 0; k < RPL; ++k)
+                        if (lp + k * np < hz)
+                            split_fetch_e<ET>(R[k], hzb);
                     if (t >= 2) {
                         int fail0 = 0;
 #pragma unroll
                         for (int k = 0; k < RPL; ++k)
                             if (lp + k * np < hz) {
                                 const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
-                                const s16x2 pe = syn0[k] ^ own ^ swap_pair(own);
+                                const s16x2 pe = syn_of(k, 0) ^ own ^ swap_pair(own);
                                 fail0 |= (pe.x | pe.y) < 0;
                             }
                         if (!block_vote(fail0, flags, vk)) {
@@ -184,26 +192,26 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     for (int k = 0; k < RPL; ++k) {
                         const int r = lp + k * np;
                         if (r < hz)
-                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R[k], lref(0, r), syn0[k], es);
+                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R[k], lref(0, r), syn_of(k, 0), es);
                     }
-                    __syncthreads();
                 }
                 for (int b = 1; b < C.mb; ++b) {
+                    SplitRow<DH> R[RPL];
+                    prepare(R, t, b);
+                    __syncthreads();
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         const int r = lp + k * np;
                         if (r < hz) {
-                            SplitRow<DH> R;
-                            const auto Lr = lref(b, r);
-                            split_load<DMIN, DMAX, ET, LG, OFF>(R, Lr, s_tab + b * DH * 2 + h, r, zm, hzb, t == 1,
-                                                                off_row(t));
-                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R, Lr, syn_of(k, b), es);
+                            split_fetch_e<ET>(R[k], hzb);
+                            split_finish<DMIN, DMAX, ET, RULE, LG, OFF>(C, R[k], lref(b, r), syn_of(k, b), es);
                         }
                     }
-                    __syncthreads();
                 }
                 iters = t;
             }
+            // the last step's E writes before the stage-out reads
+            __syncthreads();
         } else {
             // Global L, software-pipelined: one flat loop over the layer steps g
             // of all iterations, unrolled by PD so that register slot j always

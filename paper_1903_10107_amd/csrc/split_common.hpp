@@ -159,26 +159,42 @@ struct SplitRow {
     unsigned off[(DH + 1) / 2];  // magnitude offsets of the slots' blocks, 16 bits each (offset tables only)
 };
 
-// off_row: the offset table's row of the current iteration (OFF only); padding
-// slots (block -1) take offset 0.
+// Slot addresses, padding masks and (OFF) offsets of one lane's slots.
+// off_row: the offset table's row of the current iteration; padding slots
+// (block -1) take offset 0.
 template <int DMIN, int DMAX, typename ET, bool OFF = false>
-__device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *__restrict__ tab, int r, unsigned zm,
-                                             unsigned hzb, const int32_t *__restrict__ off_row = nullptr)
+__device__ __forceinline__ void split_addr(SplitRow<DMAX / 2> &R, const int4 *__restrict__ tab, int r, unsigned zm,
+                                           const int32_t *__restrict__ off_row = nullptr)
 {
     constexpr int DH = DMAX / 2;
     constexpr unsigned esh = sizeof(ET) == 2 ? 1 : 0;
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
         const int4 te = tab[2 * i];
-        const unsigned a0 = slot_addr(te, r, zm, esh);
-        R.a0[i] = a0;
+        R.a0[i] = slot_addr(te, r, zm, esh);
         R.pm[i] = te.z;
-        R.e[i] = pack_halves(lds_ld<ET>(a0), lds_ld<ET>(a0 ^ hzb));
         if constexpr (OFF) {
             const unsigned o = (unsigned)(te.w >= 0 ? off_row[te.w] : 0) & 0xffffu;
             R.off[i / 2] = i % 2 ? R.off[i / 2] | (o << 16) : o;
         }
     }
+}
+
+// E of both rows at the slot addresses
+template <typename ET, int DH>
+__device__ __forceinline__ void split_fetch_e(SplitRow<DH> &R, unsigned hzb)
+{
+#pragma unroll
+    for (int i = 0; i < DH; ++i)
+        R.e[i] = pack_halves(lds_ld<ET>(R.a0[i]), lds_ld<ET>(R.a0[i] ^ hzb));
+}
+
+template <int DMIN, int DMAX, typename ET, bool OFF = false>
+__device__ __forceinline__ void split_load_e(SplitRow<DMAX / 2> &R, const int4 *__restrict__ tab, int r, unsigned zm,
+                                             unsigned hzb, const int32_t *__restrict__ off_row = nullptr)
+{
+    split_addr<DMIN, DMAX, ET, OFF>(R, tab, r, zm, off_row);
+    split_fetch_e<ET>(R, hzb);
 }
 
 template <int DMIN, int DMAX, typename ET, bool LG, bool OFF = false>
