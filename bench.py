@@ -64,17 +64,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def traffic_summary(workload: str) -> dict:
+    """The "key: value" lines of the committed rocprofv3 counter summary of a
+    workload (empty when there is none)."""
+    path = os.path.join(PROFILES, f"decode_{workload}_traffic.txt")
+    kv = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
 def measured_traffic(workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(PROFILES, f"decode_{workload}_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+    kv = traffic_summary(workload)
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:

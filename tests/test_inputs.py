@@ -105,3 +105,13 @@ def test_learned_offsets_quantize_to_the_llr_step():
     beta = np.array([[0.0, 0.49 * d, 0.51 * d, 1.5 * d + 1e-9, 100.0, -0.3]])
     assert learn.int_offsets(beta).tolist() == [[0, 0, 1, 2, 63, 0]]
     assert learn.int_offsets(beta, msg_max=31)[0, 4] == 31
+
+
+def test_committed_traffic_summary_is_readable():
+    """The headline workload's rocprofv3 counter summary carries the two fields
+    the benchmark reads (the source hash it was taken on and the HBM bytes per
+    launch); roofline.traffic is null whenever they are missing or stale."""
+    import bench
+    kv = bench.traffic_summary("n32768_q2")
+    assert len(kv.get("kernel_source_sha256", "")) == 16
+    assert float(kv["hbm_bytes_per_dispatch"]) > 0
