@@ -359,8 +359,11 @@ def large_frames(steps, warmup):
     """Frames of n = 1048576 (10x64 QC base, Z = 16384, 16-bit soft values), 32
     frames, 80 iterations: the literal configuration at QBER 2% (every frame
     runs all 80 iterations: a fixed amount of work) and the same code shortened
-    by a third (corrected-key throughput), on the layer-synchronous family,
-    whose launches are replayed as one HIP graph."""
+    by a third (corrected-key throughput), on the layer-synchronous family.
+    Its launches are replayed as HIP graphs: the whole decode as one graph for
+    the literal case; for the shortened case one graph per iteration, with the
+    host reading the number of frames not yet retired after each and stopping
+    at 0 (check_every = 1)."""
     import numpy as np
     from paper_1903_10107_amd import inputs as I
     from paper_1903_10107_amd import metrics as M
@@ -371,16 +374,16 @@ def large_frames(steps, warmup):
     degs = [int((code.base[b] >= 0).sum()) for b in range(code.mb)]
     out = {"workload": wl.name, "code": "10x64 QC base, Z=16384, column weight 3 (n=1048576)", "frames": wl.frames,
            "max_iter": wl.max_iter, "soft_values": "int16"}
-    for name, frac in (("literal", 0.0), ("shortened_0.33", 0.33)):
+    for name, frac, check in (("literal", 0.0, 0), ("shortened_0.33", 0.33, 1)):
         fr = I.make_frames(code, wl.frames, wl.qber, 10107, n_short=int(frac * code.n))
-        # the decode is a few hundred launches: replayed as one HIP graph
-        run = tune.Runner(code.base, code.z, fr.syn, fr.llr, wl.max_iter, tune.Schedule(graph=True), None,
-                          wl.acc_bits)
+        sched = tune.Schedule(graph=True, check_every=check)
+        run = tune.Runner(code.base, code.z, fr.syn, fr.llr, wl.max_iter, sched, None, wl.acc_bits)
         ms = tune.time_ms(run, max(2, steps // 10), max(1, warmup // 2))
         bits, conv, iters = run.outputs()
         ok, und = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
         tops = algorithmic_int_ops((code.z, degs), iters.sum()) / (ms / 1e3) / 1e12
         out[name] = {"short_frac": frac, "ms_per_launch": round(ms, 3), "kernel": run.code.plan()["kernel"],
+                     "check_every": check,
                      "mean_iters": round(float(iters.mean()), 2), "fer": round(float(1 - ok.mean()), 4),
                      "mbit_s": round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2),
                      "frame_iterations_per_s": round(float(iters.sum()) / (ms / 1e3), 1),

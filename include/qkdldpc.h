@@ -179,6 +179,16 @@ typedef struct {
                                       queue hands out frames, a permutation of 0..n_frames-1
                                       (for instance hardest first); out-of-range entries are
                                       skipped. Only with persistent_workgroups > 0. */
+    int32_t check_every;           /* Layer-synchronous family (LDPC_KERNEL_LAYER_SYNC) only;
+                                      ignored by the others, whose decode is one launch that
+                                      ends with its frames. 0: every iteration up to max_iter
+                                      is enqueued and the call returns at once (launches after
+                                      a frame's retirement return immediately for it). k > 0:
+                                      after every k iterations the host waits for the stream
+                                      and reads the number of frames not yet retired; at 0 it
+                                      launches no further iterations. The call (or
+                                      ldpc_batch_launch) then returns only when the decode
+                                      has finished; results are the same. */
 } ldpc_schedule;
 
 /* ldpc_decode_batch_ex with a schedule (NULL = default). The decoded results do
@@ -193,7 +203,11 @@ int ldpc_decode_batch_sched(const ldpc_code *code, const uint8_t *syndromes, con
 size_t ldpc_workspace_bytes_sched(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched);
 
 /* A decode of fixed buffers captured once as a HIP graph (the queue reset and the
- * decode kernel), replayed by ldpc_batch_launch with one graph launch. All
+ * decode kernel), replayed by ldpc_batch_launch with one graph launch. With
+ * sched->check_every = k > 0 on the layer-synchronous family the batch holds a
+ * graph for the stage-in, one per block of k iterations and one for the
+ * stage-out, and ldpc_batch_launch replays the blocks until every frame has
+ * retired (it waits for the stream after each block). All
  * pointers are DEVICE pointers that must stay valid for the life of the batch;
  * the workspace, when one is needed and not given, is allocated at create and
  * freed at destroy. The code handle must outlive the batch. */

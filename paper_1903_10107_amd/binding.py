@@ -46,7 +46,7 @@ class ldpc_params(C.Structure):
 
 
 class ldpc_schedule(C.Structure):
-    _fields_ = [("persistent_workgroups", C.c_int32), ("order", C.c_void_p)]
+    _fields_ = [("persistent_workgroups", C.c_int32), ("order", C.c_void_p), ("check_every", C.c_int32)]
 
 
 _lib = None
@@ -259,10 +259,10 @@ def ldpc_decode_batch(code: Code, syndromes, llr_in, n_frames: int, max_iter: in
     _check(lib().ldpc_decode_batch(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, _stream_ptr(stream)))
 
 
-def _schedule(n_frames: int, persistent_workgroups: int, order):
+def _schedule(n_frames: int, persistent_workgroups: int, order, check_every: int = 0):
     import torch
     p_order = _dev_ptr(order, torch.int32, (n_frames,), "order")
-    return ldpc_schedule(int(persistent_workgroups), p_order)
+    return ldpc_schedule(int(persistent_workgroups), p_order, int(check_every))
 
 
 def ldpc_workspace_bytes_sched(code: Code, n_frames: int, persistent_workgroups: int = 0) -> int:
@@ -271,7 +271,8 @@ def ldpc_workspace_bytes_sched(code: Code, n_frames: int, persistent_workgroups:
 
 
 def ldpc_decode_batch_sched(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
-                            out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, stream=None):
+                            out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, stream=None,
+                            check_every: int = 0):
     import torch
     F = int(n_frames)
     if F < 0:
@@ -284,7 +285,7 @@ def ldpc_decode_batch_sched(code: Code, syndromes, llr_in, n_frames: int, max_it
     p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
     p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
     p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
-    sch = _schedule(F, persistent_workgroups, order)
+    sch = _schedule(F, persistent_workgroups, order, check_every)
     need = int(lib().ldpc_workspace_bytes_sched(code.handle, F, C.byref(sch)))
     p_ws, ws_bytes = None, 0
     if workspace is not None:
@@ -298,7 +299,7 @@ class Batch:
     """A decode of fixed device buffers captured as a HIP graph (ldpc_batch_*)."""
 
     def __init__(self, code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
-                 out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None):
+                 out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, check_every: int = 0):
         import torch
         self._h = None
         F = int(n_frames)
@@ -309,7 +310,7 @@ class Batch:
         p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
         p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
         p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
-        sch = _schedule(F, persistent_workgroups, order)
+        sch = _schedule(F, persistent_workgroups, order, check_every)
         need = int(lib().ldpc_workspace_bytes_sched(code.handle, F, C.byref(sch)))
         p_ws, ws_bytes = None, 0
         if workspace is not None:

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/qkdldpc.h"
 #include "decoder.hpp"
@@ -223,7 +224,8 @@ bool is_persistent(const ldpc_schedule *sched) { return sched && sched->persiste
 
 // Queue slot (persistent) plus one state slice per frame, or per persistent
 // workgroup for the split kernel, whose slices belong to workgroups.
-size_t layer_sync_flag_bytes(int32_t n_frames) { return round_up((size_t)n_frames * 16, 256); }
+// Layer-synchronous family: per-frame flags, then the count of frames not yet retired.
+size_t layer_sync_flag_bytes(int32_t n_frames) { return round_up((size_t)n_frames * 16, 256) + 256; }
 
 size_t workspace_need(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched)
 {
@@ -252,6 +254,8 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
             return fail(LDPC_EINVAL, "ldpc_schedule: order needs persistent_workgroups > 0");
         if (sched->persistent_workgroups > 0 && (!code->plan.split_dmax || code->plan.layer_sync))
             return fail(LDPC_EUNSUPPORTED, "ldpc_schedule: persistent workgroups need the split kernel family");
+        if (sched->check_every < 0)
+            return fail(LDPC_EINVAL, "ldpc_schedule: check_every < 0");
     }
     return LDPC_OK;
 }
@@ -278,8 +282,11 @@ DecodeArgs make_args(const ldpc_code *code, const uint8_t *syndromes, const int8
         w += kQueueBytes;
     }
     A.ws = code->ws_frame_bytes ? w : nullptr;
-    if (code->plan.layer_sync)
+    if (code->plan.layer_sync) {
         A.mflags = reinterpret_cast<int *>(w + code->ws_frame_bytes * (size_t)n_frames);
+        A.mcount = reinterpret_cast<int *>(reinterpret_cast<uint8_t *>(A.mflags) +
+                                           round_up((size_t)n_frames * 16, 256));
+    }
     A.ws_frame_bytes = code->ws_frame_bytes;
     A.ws_l_off = code->ws_l_off;
     A.syn_bytes = (code->h.m + 7) / 8;
@@ -295,6 +302,45 @@ DecodeArgs make_args(const ldpc_code *code, const uint8_t *syndromes, const int8
                                                                     code->lane_tab_bytes)
                                : nullptr;
     return A;
+}
+
+bool early_stop(const ldpc_code *code, const ldpc_schedule *sched)
+{
+    return code->plan.layer_sync && sched && sched->check_every > 0;
+}
+
+// Frames of a layer-synchronous decode not yet retired, read after the stream
+// has drained (host is pinned memory or, with nullptr, a stack variable).
+hipError_t active_frames(const DecodeArgs &A, int *host, hipStream_t s, int *out)
+{
+    int local = 0;
+    int *dst = host ? host : &local;
+    hipError_t e = hipMemcpyAsync(dst, A.mcount, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    *out = *dst;
+    return e;
+}
+
+// Layer-synchronous decode that stops launching once every frame has retired:
+// the active count is read after the iteration-0 check and after every k
+// iterations.
+hipError_t decode_early_stop(const ldpc_code *code, const DecodeArgs &A, int k, hipStream_t s)
+{
+    const LaunchPlan &P = code->plan;
+    hipError_t e = qkdldpc::launch_multi_head(P, code->dev, A, s);
+    int active = 0;
+    if (e == hipSuccess)
+        e = active_frames(A, nullptr, s, &active);
+    for (int t = 1; e == hipSuccess && active > 0 && t <= A.max_iter; t += k) {
+        const int t1 = std::min(A.max_iter, t + k - 1);
+        e = qkdldpc::launch_multi_iters(P, code->dev, A, t, t1, s);
+        if (e == hipSuccess)
+            e = active_frames(A, nullptr, s, &active);
+    }
+    if (e == hipSuccess)
+        e = qkdldpc::launch_multi_tail(P, code->dev, A, s);
+    return e;
 }
 
 int decode_impl(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
@@ -323,7 +369,8 @@ int decode_impl(const ldpc_code *code, const uint8_t *syndromes, const int8_t *l
     }
     const DecodeArgs A = make_args(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, out_iters,
                                    out_L, out_E, sched, ws);
-    hipError_t e = qkdldpc::launch_decode(code->plan, code->dev, A, s);
+    hipError_t e = early_stop(code, sched) ? decode_early_stop(code, A, sched->check_every, s)
+                                           : qkdldpc::launch_decode(code->plan, code->dev, A, s);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, s);
         if (e == hipSuccess)
@@ -412,8 +459,13 @@ qkdldpc::OmsArgs oms_args(const ldpc_code *code, const uint8_t *syndromes, const
 } // namespace
 
 struct ldpc_batch {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // one graph for the whole decode, or (early stop) stage-in, blocks of
+    // iterations and stage-out
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
+    bool early_stop = false;
+    DecodeArgs args{};
+    int *host_count = nullptr;  // pinned: frames not yet retired (early stop)
     void *owned_ws = nullptr;
     int device = -1;
 };
@@ -634,17 +686,43 @@ int ldpc_batch_create(const ldpc_code *code, const uint8_t *syndromes, const int
     }
     const DecodeArgs A = make_args(code, syndromes, llr_in, n_frames, max_iter, out_bits, out_converged, out_iters,
                                    nullptr, nullptr, sched, ws);
+    b->args = A;
+    b->early_stop = early_stop(code, sched);
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess)
-        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t el = qkdldpc::launch_decode(code->plan, code->dev, A, cs);
-        hipError_t ec = hipStreamEndCapture(cs, &b->graph);
-        e = el != hipSuccess ? el : ec;
+    // capture one launch sequence into the next graph of the batch
+    auto capture = [&](auto &&enqueue) {
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (ee != hipSuccess)
+            return ee;
+        hipError_t el = enqueue();
+        hipError_t ec = hipStreamEndCapture(cs, &g);
+        if (g)
+            b->graphs.push_back(g);
+        ee = el != hipSuccess ? el : ec;
+        hipGraphExec_t x = nullptr;
+        if (ee == hipSuccess)
+            ee = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (x)
+            b->execs.push_back(x);
+        return ee;
+    };
+    const LaunchPlan &P = code->plan;
+    if (e == hipSuccess && !b->early_stop) {
+        e = capture([&] { return qkdldpc::launch_decode(P, code->dev, A, cs); });
+    } else if (e == hipSuccess) {
+        const int k = sched->check_every;
+        e = hipHostMalloc(reinterpret_cast<void **>(&b->host_count), sizeof(int), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = capture([&] { return qkdldpc::launch_multi_head(P, code->dev, A, cs); });
+        for (int t = 1; e == hipSuccess && t <= max_iter; t += k) {
+            const int t1 = std::min(max_iter, t + k - 1);
+            e = capture([&] { return qkdldpc::launch_multi_iters(P, code->dev, A, t, t1, cs); });
+        }
+        if (e == hipSuccess)
+            e = capture([&] { return qkdldpc::launch_multi_tail(P, code->dev, A, cs); });
     }
-    if (e == hipSuccess)
-        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (cs)
         (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
@@ -665,7 +743,26 @@ int ldpc_batch_launch(ldpc_batch *batch, void *stream)
         return hip_fail("hipGetDevice", e);
     if (cur != batch->device)
         return fail(LDPC_EINVAL, "ldpc_batch_launch: batch was created on another device");
-    e = hipGraphLaunch(batch->exec, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!batch->early_stop) {
+        e = hipGraphLaunch(batch->execs[0], s);
+        if (e != hipSuccess)
+            return hip_fail("ldpc_batch_launch: hipGraphLaunch", e);
+        return LDPC_OK;
+    }
+    // stage-in, then blocks of iterations while frames remain, then stage-out
+    const size_t nx = batch->execs.size();
+    int active = 0;
+    e = hipGraphLaunch(batch->execs[0], s);
+    if (e == hipSuccess)
+        e = active_frames(batch->args, batch->host_count, s, &active);
+    for (size_t i = 1; e == hipSuccess && active > 0 && i + 1 < nx; ++i) {
+        e = hipGraphLaunch(batch->execs[i], s);
+        if (e == hipSuccess)
+            e = active_frames(batch->args, batch->host_count, s, &active);
+    }
+    if (e == hipSuccess)
+        e = hipGraphLaunch(batch->execs[nx - 1], s);
     if (e != hipSuccess)
         return hip_fail("ldpc_batch_launch: hipGraphLaunch", e);
     return LDPC_OK;
@@ -675,10 +772,12 @@ void ldpc_batch_destroy(ldpc_batch *batch)
 {
     if (!batch)
         return;
-    if (batch->exec)
-        (void)hipGraphExecDestroy(batch->exec);
-    if (batch->graph)
-        (void)hipGraphDestroy(batch->graph);
+    for (hipGraphExec_t x : batch->execs)
+        (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : batch->graphs)
+        (void)hipGraphDestroy(g);
+    if (batch->host_count)
+        (void)hipHostFree(batch->host_count);
     if (batch->owned_ws)
         (void)hipFree(batch->owned_ws);
     delete batch;

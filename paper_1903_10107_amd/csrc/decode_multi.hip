@@ -88,6 +88,8 @@ __global__ __launch_bounds__(256) void k_multi_stage_in(DevCode C, DecodeArgs A)
         frame_flags(A, f)[0] = 1;
         frame_flags(A, f)[1] = 0;
         frame_flags(A, f)[2] = 0;
+        if (f == 0)
+            *A.mcount = A.n_frames;
     }
 }
 
@@ -155,12 +157,14 @@ __global__ __launch_bounds__(256) void k_multi_finalize(DecodeArgs A, int t)
             A.out_conv[f] = 1;
             if (A.out_iters)
                 A.out_iters[f] = t;
+            atomicSub(A.mcount, 1);
         } else if (t >= A.max_iter) {
             fl[0] = 0;
             fl[2] = A.max_iter;
             A.out_conv[f] = 0;
             if (A.out_iters)
                 A.out_iters[f] = A.max_iter;
+            atomicSub(A.mcount, 1);
         }
     }
     fl[1] = 0;
@@ -241,57 +245,98 @@ __global__ __launch_bounds__(256) void k_multi_stage_out(DevCode C, DecodeArgs A
 
 namespace {
 
+// Launch phases: stage-in and the iteration-0 check and retirement (0),
+// iterations t0..t1 (1), stage-out (2).
 template <int DMIN, int DMAX, typename ET, int RULE>
-hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
+                     hipStream_t s)
 {
     const int F = A.n_frames, hz = C.z / 2;
     const int np = P.threads / 2;
     const dim3 rows((hz + np - 1) / np, F);
     const dim3 elems((C.n + 1023) / 1024 < 64 ? (C.n + 1023) / 1024 : 64, F);
     const dim3 fin((F + 255) / 256);
-    hipLaunchKernelGGL((k_multi_stage_in<ET>), elems, dim3(256), 0, s, C, A);
-    hipLaunchKernelGGL((k_multi_check<DMIN, DMAX, ET>), rows, dim3(P.threads), 0, s, C, A);
-    hipLaunchKernelGGL(k_multi_finalize, fin, dim3(256), 0, s, A, 0);
-    hipError_t e = hipGetLastError();
-    for (int t = 1; t <= A.max_iter && e == hipSuccess; ++t) {
+    if (phase == 0) {
+        hipLaunchKernelGGL((k_multi_stage_in<ET>), elems, dim3(256), 0, s, C, A);
+        hipLaunchKernelGGL((k_multi_check<DMIN, DMAX, ET>), rows, dim3(P.threads), 0, s, C, A);
+        hipLaunchKernelGGL(k_multi_finalize, fin, dim3(256), 0, s, A, 0);
+        return hipGetLastError();
+    }
+    if (phase == 2) {
+        hipLaunchKernelGGL((k_multi_stage_out<DMAX, ET>), elems, dim3(256), 0, s, C, A);
+        return hipGetLastError();
+    }
+    hipError_t e = hipSuccess;
+    for (int t = t0; t <= t1 && e == hipSuccess; ++t) {
         for (int b = 0; b < C.mb; ++b)
             hipLaunchKernelGGL((k_multi_layer<DMIN, DMAX, ET, RULE>), rows, dim3(P.threads), 0, s, C, A, b, t);
         hipLaunchKernelGGL((k_multi_check<DMIN, DMAX, ET>), rows, dim3(P.threads), 0, s, C, A);
         hipLaunchKernelGGL(k_multi_finalize, fin, dim3(256), 0, s, A, t);
         e = hipGetLastError();
     }
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((k_multi_stage_out<DMAX, ET>), elems, dim3(256), 0, s, C, A);
-    return hipGetLastError();
+    return e;
 }
 
 template <int DMIN, int DMAX, typename ET>
-hipError_t run_rule(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+hipError_t run_rule(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
+                    hipStream_t s)
 {
     if (P.cn_rule == LDPC_RULE_MINSUM)
-        return run_multi<DMIN, DMAX, ET, kRuleMinSum>(P, C, A, s);
-    return run_multi<DMIN, DMAX, ET, kRuleRcbpFB>(P, C, A, s);
+        return run_multi<DMIN, DMAX, ET, kRuleMinSum>(P, C, A, phase, t0, t1, s);
+    return run_multi<DMIN, DMAX, ET, kRuleRcbpFB>(P, C, A, phase, t0, t1, s);
 }
 
 template <typename ET>
-hipError_t run_et(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+hipError_t run_et(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
+                  hipStream_t s)
 {
     switch (P.split_dmax) {
     case 6:
-        return run_rule<6, 6, ET>(P, C, A, s);
+        return run_rule<6, 6, ET>(P, C, A, phase, t0, t1, s);
     case 8:
-        return P.min_deg >= 6 ? run_rule<6, 8, ET>(P, C, A, s) : run_rule<2, 8, ET>(P, C, A, s);
+        return P.min_deg >= 6 ? run_rule<6, 8, ET>(P, C, A, phase, t0, t1, s)
+                              : run_rule<2, 8, ET>(P, C, A, phase, t0, t1, s);
     default:
-        return P.min_deg >= 19 ? run_rule<19, 20, ET>(P, C, A, s) : run_rule<2, 20, ET>(P, C, A, s);
+        return P.min_deg >= 19 ? run_rule<19, 20, ET>(P, C, A, phase, t0, t1, s)
+                               : run_rule<2, 20, ET>(P, C, A, phase, t0, t1, s);
     }
+}
+
+hipError_t run_phase(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
+                     hipStream_t s)
+{
+    return P.acc_bits == 16 ? run_et<int16_t>(P, C, A, phase, t0, t1, s)
+                            : run_et<int8_t>(P, C, A, phase, t0, t1, s);
 }
 
 } // namespace
 
+hipError_t launch_multi_head(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+{
+    return run_phase(P, C, A, 0, 0, 0, s);
+}
+
+hipError_t launch_multi_iters(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int t0, int t1,
+                              hipStream_t s)
+{
+    return run_phase(P, C, A, 1, t0, t1, s);
+}
+
+hipError_t launch_multi_tail(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
+{
+    return run_phase(P, C, A, 2, 0, 0, s);
+}
+
+// The whole decode, every iteration enqueued (retired frames make the later
+// launches return at once).
 hipError_t launch_decode_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
-    return P.acc_bits == 16 ? run_et<int16_t>(P, C, A, s) : run_et<int8_t>(P, C, A, s);
+    hipError_t e = launch_multi_head(P, C, A, s);
+    if (e == hipSuccess && A.max_iter > 0)
+        e = launch_multi_iters(P, C, A, 1, A.max_iter, s);
+    if (e == hipSuccess)
+        e = launch_multi_tail(P, C, A, s);
+    return e;
 }
 
 } // namespace qkdldpc

@@ -33,6 +33,7 @@ struct DecodeArgs {
     int *queue;           // persistent: device counter (reset by k_queue_reset)
     const int32_t *order; // persistent: decode order, a permutation of the frames, or nullptr
     int *mflags;          // layer-synchronous family: per frame {active, unsat, iterations, -}
+    int *mcount;          // layer-synchronous family: number of frames not yet retired
 };
 
 struct LaunchPlan {
@@ -54,6 +55,12 @@ hipError_t launch_decode_scalar(const LaunchPlan &P, const DevCode &C, const Dec
 hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+// The layer-synchronous decode in three phases, for callers that stop early:
+// stage-in and the iteration-0 check; iterations t0..t1; stage-out.
+hipError_t launch_multi_head(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+hipError_t launch_multi_iters(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int t0, int t1,
+                              hipStream_t s);
+hipError_t launch_multi_tail(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s);
 hipError_t launch_queue_reset(int *queue, hipStream_t s);
 hipError_t launch_reveal(int8_t *llr, int n, int n_frames, const int32_t *frame_ids, int k, const int32_t *positions,

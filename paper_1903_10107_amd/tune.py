@@ -11,7 +11,9 @@ a representative batch held on the GPU and keeps the fastest:
   its expected iteration count), which moves long frames away from the end of
   the launch;
 * graph: the decode captured once as a HIP graph and replayed, or launched
-  directly.
+  directly;
+* early stop (layer-synchronous family only): the host reads the number of
+  frames not yet retired after every iteration and stops launching at 0.
 
 Every candidate must produce identical outputs (the schedule never changes the
 results); a mismatch raises. Results are cached in a JSON file keyed by the
@@ -39,6 +41,7 @@ class Schedule:
     persistent_workgroups: int = 0
     order: str = "none"          # "none" or "hardest_first"
     graph: bool = False
+    check_every: int = 0         # layer-synchronous family: iterations between host checks (0: none)
 
 
 def _key(base, z, n_frames, max_iter, acc_bits, has_difficulty) -> str:
@@ -55,6 +58,8 @@ def candidates(n_cu: int, has_difficulty: bool) -> list[Schedule]:
     for kernel in ("split", "split_global_l", "layer_sync", "pairs", "lds", "global"):
         out.append(Schedule(kernel, 0, "none", False))
         out.append(Schedule(kernel, 0, "none", True))
+    for graph in (False, True):
+        out.append(Schedule("layer_sync", 0, "none", graph, 1))
     for kernel in B.PERSISTENT_FAMILIES:
         for wgs in (n_cu, 2 * n_cu):
             for order in (("none", "hardest_first") if has_difficulty else ("none",)):
@@ -89,14 +94,15 @@ class Runner:
         self.batch = None
         if sched.graph:
             self.batch = B.Batch(self.code, self.syn, self.llr, F, max_iter, self.bits, self.conv, self.iters,
-                                 sched.persistent_workgroups, self.order, self.ws)
+                                 sched.persistent_workgroups, self.order, self.ws, check_every=sched.check_every)
 
     def __call__(self):
         if self.batch is not None:
             self.batch.launch()
         else:
             B.ldpc_decode_batch_sched(self.code, self.syn, self.llr, self.F, self.max_iter, self.bits, self.conv,
-                                      self.iters, self.sched.persistent_workgroups, self.order, self.ws)
+                                      self.iters, self.sched.persistent_workgroups, self.order, self.ws,
+                                      check_every=self.sched.check_every)
 
     def outputs(self):
         return self.bits.cpu().numpy(), self.conv.cpu().numpy(), self.iters.cpu().numpy()

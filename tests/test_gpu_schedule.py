@@ -174,3 +174,62 @@ def test_graph_of_a_layer_synchronous_decode_replays(B):
         assert np.array_equal(gb.cpu().numpy(), ref["bits"]), rep
         assert np.array_equal(gi.cpu().numpy(), ref["iters"]), rep
     del batch
+
+
+@pytest.mark.parametrize("check_every,graph", [(1, False), (3, False), (1, True), (4, True)])
+def test_layer_sync_early_stop_matches_oracle(B, check_every, graph):
+    """check_every > 0: the host stops launching iterations once every frame has
+    retired; the results are those of the full decode (frames converge at
+    different iterations, one frame runs out of iterations, and max_iter is not
+    a multiple of check_every)."""
+    import torch
+    code = I.Code(I.make_base(5, 32, 256), 256)
+    q = np.full(10, 0.02)
+    q[3] = 0.2                                   # cannot converge: runs all max_iter iterations
+    fr = I.make_frames(code, 10, q, 71, n_short=int(0.3 * code.n))
+    gc = B.Code(code.base, code.z, kernel="layer_sync")
+    syn, llr = torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda()
+    F, T = fr.n_frames, 13
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, T)
+    assert ref["conv"][3] == 0 and ref["iters"].min() < T
+    _say(f"[gpu early stop] check_every={check_every} graph={graph} iters={ref['iters'].tolist()}")
+    bits, conv, iters = _outs(code, F)
+    if graph:
+        batch = B.Batch(gc, syn, llr, F, T, bits, conv, iters, check_every=check_every)
+        for rep in range(2):
+            bits.zero_()
+            iters.fill_(-1)
+            batch.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(bits.cpu().numpy(), ref["bits"]), rep
+            assert np.array_equal(conv.cpu().numpy(), ref["conv"]), rep
+            assert np.array_equal(iters.cpu().numpy(), ref["iters"]), rep
+        del batch
+    else:
+        B.ldpc_decode_batch_sched(gc, syn, llr, F, T, bits, conv, iters, check_every=check_every)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+        assert np.array_equal(conv.cpu().numpy(), ref["conv"])
+        assert np.array_equal(iters.cpu().numpy(), ref["iters"])
+
+
+def test_early_stop_all_converged_at_iteration_0_and_argument_errors(B):
+    import torch
+    code = I.Code(I.make_base(5, 32, 64), 64)
+    fr = I.make_frames(code, 4, 1e-9, 5)         # no errors: every frame satisfies the syndrome at once
+    gc = B.Code(code.base, code.z, kernel="layer_sync")
+    syn, llr = torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda()
+    bits, conv, iters = _outs(code, 4)
+    B.ldpc_decode_batch_sched(gc, syn, llr, 4, 20, bits, conv, iters, check_every=2)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, 20)
+    assert np.array_equal(iters.cpu().numpy(), ref["iters"]) and ref["iters"].max() == 0
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+    with pytest.raises(B.LdpcError) as ei:
+        B.ldpc_decode_batch_sched(gc, syn, llr, 4, 20, bits, conv, iters, check_every=-1)
+    assert ei.value.code == B.LDPC_EINVAL
+    sp = B.Code(code.base, code.z)                # split family: check_every is ignored
+    assert sp.plan()["kernel"] == "split"
+    B.ldpc_decode_batch_sched(sp, syn, llr, 4, 20, bits, conv, iters, check_every=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
