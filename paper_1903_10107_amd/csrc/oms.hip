@@ -77,15 +77,30 @@ struct RowMin {
 
 __device__ __forceinline__ bool lex_less(float a, int ia, float b, int ib) { return a < b || (a == b && ia < ib); }
 
-// Combine with the quad partner at xor distance o.
-__device__ __forceinline__ RowMin quad_combine(RowMin a, int o)
+// Value of the quad partner at xor distance O (1 or 2): a DPP quad permutation,
+// [1,0,3,2] or [2,3,0,1]; every lane of the wave takes part.
+template <int O>
+__device__ __forceinline__ int quad_xor(int x)
+{
+    static_assert(O == 1 || O == 2, "quad partner");
+    return __builtin_amdgcn_update_dpp(0, x, O == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int O>
+__device__ __forceinline__ float quad_xor(float x)
+{
+    return __builtin_bit_cast(float, quad_xor<O>(__builtin_bit_cast(int, x)));
+}
+
+// Combine with the quad partner at xor distance O.
+template <int O>
+__device__ __forceinline__ RowMin quad_combine(RowMin a)
 {
     RowMin b;
-    b.m1 = __shfl_xor(a.m1, o, 64);
-    b.m2 = __shfl_xor(a.m2, o, 64);
-    b.i1 = __shfl_xor(a.i1, o, 64);
-    b.i2 = __shfl_xor(a.i2, o, 64);
-    b.par = __shfl_xor(a.par, o, 64);
+    b.m1 = quad_xor<O>(a.m1);
+    b.m2 = quad_xor<O>(a.m2);
+    b.i1 = quad_xor<O>(a.i1);
+    b.i2 = quad_xor<O>(a.i2);
+    b.par = quad_xor<O>(a.par);
     RowMin r;
     r.par = a.par ^ b.par;
     const bool aw = lex_less(a.m1, a.i1, b.m1, b.i1);
@@ -101,12 +116,13 @@ __device__ __forceinline__ RowMin quad_combine(RowMin a, int o)
 
 struct OmsState {
     float *E, *L;      // E [n], L [n_blocks * Z] (forward) or their adjoints (backward)
+    int2 *blk;         // per block {column start c*Z, circulant shift}, staged in LDS
     float *beta;       // offsets [T][n_blocks] staged in LDS
     float *red;        // reduction scratch
     uint8_t *syn;      // packed syndrome of the frame
 };
 
-// LDS: [state if LDS] [beta T * n_blocks] [red] [syndrome]
+// LDS: [state if LDS] [block table, 16-byte aligned] [beta T * n_blocks] [red] [syndrome]
 __device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A, bool lds, int red_floats)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -116,11 +132,13 @@ __device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A
     if (lds) {
         S.E = reinterpret_cast<float *>(p);
         S.L = S.E + C.n;
-        p += (C.n + ne) * sizeof(float);
+        p += ((C.n + ne) * sizeof(float) + 15) & ~(size_t)15;
     } else {
         S.E = A.state + (size_t)blockIdx.x * (C.n + ne);
         S.L = S.E + C.n;
     }
+    S.blk = reinterpret_cast<int2 *>(p);
+    p += (size_t)C.n_blocks * sizeof(int2);
     S.beta = reinterpret_cast<float *>(p);
     p += (size_t)A.n_iter * C.n_blocks * sizeof(float);
     S.red = reinterpret_cast<float *>(p);
@@ -137,6 +155,8 @@ __device__ __forceinline__ void stage_common(const DevCode &C, const OmsArgs &A,
         S.syn[i] = syn[i];
     for (int i = tid; i < A.n_iter * C.n_blocks; i += nthr)
         S.beta[i] = A.beta[i];
+    for (int i = tid; i < C.n_blocks; i += nthr)
+        S.blk[i] = int2{ldc(C.colbase, i), ldc(C.shift, i)};
 }
 
 } // namespace
@@ -188,8 +208,8 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                     v[s] = 0.f;
                     col[s] = 0;
                     if (act && k < d) {
-                        const int blk = o + k;
-                        const int j = ldc(C.colbase, blk) + rot(r, ldc(C.shift, blk), z);
+                        const int2 cs = S.blk[o + k];
+                        const int j = cs.x + rot(r, cs.y, z);
                         const size_t le = lb + (size_t)r * d + k;
                         const float vk = E[j] - L[le];
                         tv[le] = vk;
@@ -208,8 +228,8 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                         }
                     }
                 }
-                M = quad_combine(M, 1);
-                M = quad_combine(M, 2);
+                M = quad_combine<1>(M);
+                M = quad_combine<2>(M);
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
@@ -264,6 +284,20 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
     const float *tape = A.tape + (size_t)f * T * (ne + n);
     const uint8_t *xb = A.xbits + (size_t)f * A.bit_bytes;
     const float g = A.dloss[f] / (float)n;
+    // The tape's v of the next row chunk in walk order (layers and iterations in
+    // reverse) is requested while the current chunk is processed, so its global
+    // latency overlaps that work and the layer barriers.
+    float vnext[SL];
+    auto fetch_v = [&](int t, int b, int r0) {
+        const int d = ldc(C.deg, b), r = r0 + rq;
+        const float *tvl = tape + (size_t)t * (ne + n) + (size_t)ldc(C.blk_off, b) * z;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int k = q * SL + s;
+            vnext[s] = r < z && k < d ? tvl[(size_t)r * d + k] : 0.f;
+        }
+    };
+    fetch_v(T - 1, C.mb - 1, 0);
     for (int t = T - 1; t >= 0; --t) {
         const float *bt = S.beta + t * C.n_blocks;
         const float *tv = tape + (size_t)t * (ne + n);
@@ -286,6 +320,15 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                 const bool act = r < z;
                 float v[SL], vb[SL];
                 int col[SL];
+#pragma unroll
+                for (int s = 0; s < SL; ++s)
+                    v[s] = vnext[s];
+                if (r0 + nq < z)
+                    fetch_v(t, b, r0 + nq);
+                else if (b > 0)
+                    fetch_v(t, b - 1, 0);
+                else if (t > 0)
+                    fetch_v(t - 1, C.mb - 1, 0);
                 RowMin M;
                 M.m1 = M.m2 = INFINITY;
                 M.i1 = M.i2 = DMAX;
@@ -297,13 +340,11 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
-                    v[s] = 0.f;
                     col[s] = 0;
                     if (act && k < d) {
-                        const int blk = o + k;
-                        col[s] = ldc(C.colbase, blk) + rot(r, ldc(C.shift, blk), z);
-                        const float vk = tv[lb + (size_t)r * d + k];
-                        v[s] = vk;
+                        const int2 cs = S.blk[o + k];
+                        col[s] = cs.x + rot(r, cs.y, z);
+                        const float vk = v[s];
                         M.par ^= vk < 0.f;
                         const float a = fabsf(vk);
                         if (a < M.m1) {
@@ -317,8 +358,8 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                         }
                     }
                 }
-                M = quad_combine(M, 1);
-                M = quad_combine(M, 2);
+                M = quad_combine<1>(M);
+                M = quad_combine<2>(M);
                 // adjoint of L_k (new) = its own adjoint + that of E_{j_k} (E = v + L)
                 float g_rest = 0.f, g_i1 = 0.f;
 #pragma unroll
@@ -341,10 +382,10 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                     }
                 }
                 // every k != i1 read |v_i1|, k = i1 read |v_i2|: sum over the quad
-                g_rest += __shfl_xor(g_rest, 1, 64);
-                g_rest += __shfl_xor(g_rest, 2, 64);
-                g_i1 += __shfl_xor(g_i1, 1, 64);
-                g_i1 += __shfl_xor(g_i1, 2, 64);
+                g_rest += quad_xor<1>(g_rest);
+                g_rest += quad_xor<2>(g_rest);
+                g_i1 += quad_xor<1>(g_i1);
+                g_i1 += quad_xor<2>(g_i1);
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
