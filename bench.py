@@ -109,9 +109,21 @@ def cpu_baseline(code, fr, wl, seconds: float):
         ok, _ = M.frame_outcomes(fr.x[sl], I.unpack_bits(r["bits"], code.n), r["conv"])
         bits_ok += int(fr.key_bits()[sl][ok].sum())
         done += sl.stop - sl.start
+    # the same oracle on one thread, over a smaller sample (a few frames)
+    t1, ok1, n1 = 0.0, 0, 0
+    while t1 < min(3.0, seconds / 4):
+        sl = slice(n1 % fr.n_frames, n1 % fr.n_frames + 1)
+        t = time.perf_counter()
+        r = O.decode(code.base, code.z, fr.syn[sl], fr.llr[sl], wl.max_iter, acc_bits=wl.acc_bits, n_threads=1)
+        t1 += time.perf_counter() - t
+        ok, _ = M.frame_outcomes(fr.x[sl], I.unpack_bits(r["bits"], code.n), r["conv"])
+        ok1 += int(fr.key_bits()[sl][ok].sum())
+        n1 += 1
     return {"value": round(bits_ok / elapsed / 1e6, 3), "unit": "Mbit/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} frame decodes cycling over the {fr.n_frames} frames of the same workload "
-                      f"(oracle, {threads} OpenMP threads over frames, {elapsed:.1f} s of decoding)"}
+                      f"(oracle, {threads} OpenMP threads over frames, {elapsed:.1f} s of decoding)",
+            "single_thread": {"value": round(ok1 / t1 / 1e6, 3), "unit": "Mbit/s", "cores": 1,
+                              "sample": f"{n1} frame decodes of the same batch on one thread, {t1:.1f} s"}}
 
 
 def copy_calibration(nbytes: int, steps: int, warmup: int):
