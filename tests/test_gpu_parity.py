@@ -204,3 +204,23 @@ def test_parity_full_n32768_sampled(B):
 
 def test_parity_full_n1048576_sampled(B):
     _full_size(B, "n1048576_q2", sample=np.array([0, 31]))
+
+
+@pytest.mark.parametrize("kernel", ["split", "pairs", "global", "layer_sync"])
+@pytest.mark.parametrize("mode", ["saturated", "zero", "small"])
+def test_degenerate_channel_values(B, mode, kernel):
+    """Soft inputs at the edges of the method: every |E| = E_max from the start
+    (Alg. 2 freezes every variable, so the state never moves), all zero (every
+    sign is +, every check-node input magnitude 0), and all of magnitude 1 (the
+    check node's small-value branch of Alg. 1 everywhere)."""
+    code = I.Code(I.make_base(5, 32, 64), 64)
+    fr = I.make_frames(code, 8, 0.03, 4242)
+    sign = np.where(fr.llr < 0, -1, 1).astype(np.int16)
+    llr = {"saturated": 127 * sign, "zero": 0 * sign, "small": 3 * sign}[mode].astype(np.int8)
+    gc = B.Code(code.base, code.z, kernel=kernel)
+    _say(f"[gpu parity] degenerate {mode} on {gc.plan()}")
+    got = B.decode(gc, fr.syn, llr, 20, want_state=True)
+    ref = O.decode(code.base, code.z, fr.syn, llr, 20, want_state=True)
+    _compare(got, ref)
+    if mode == "saturated":
+        assert np.array_equal(ref["E"], llr.astype(np.int16)), "frozen state moved"
