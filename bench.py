@@ -367,6 +367,31 @@ def retry_figure(n_frames, extra=2048, step=512, max_rounds=12):
     return out
 
 
+def lds_peaks(reps: int = 256, n_wg: int = 2048) -> dict:
+    """Measured LDS read bandwidth of the whole chip (GB/s) for 16-byte and for
+    byte reads (ldpc_probe_lds_bandwidth: conflict-free reads, 1024-thread
+    workgroups of 64 KB each, two per CU), median of five launches."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+
+    out = torch.zeros(n_wg * 1024, dtype=torch.int32, device="cuda")
+    res = {}
+    for mode, width in ((0, 16), (1, 1)):
+        B.ldpc_probe_lds_bandwidth(mode, n_wg, reps, out)
+        times = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            B.ldpc_probe_lds_bandwidth(mode, n_wg, reps, out)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        res["read_b128" if mode == 0 else "read_u8"] = round(n_wg * 1024.0 * reps * 8 * width / (ms / 1e3) / 1e9, 1)
+    return res
+
+
 def pipelined(gc, code, fr, d_syn, d_llr, max_iter, ref, steps, warmup, n_streams=2):
     """The headline workload (256-frame batches, one launch each) with
     consecutive batches issued on alternating streams, so that the CUs freed by
@@ -602,6 +627,20 @@ def main():
         "max_iters_in_batch": int(iters.max()),
         "paper_context": "57.6 Mbit/s at f=1.108 on a 4-core i7-6700HQ with its own irregular codes (context only)",
     }
+    if gc.plan()["kernel"] in ("split", "pairs", "lds"):
+        # the decoder state lives in LDS: its state traffic against the measured
+        # LDS read peaks (byte reads are the width of the decoder's accesses)
+        peaks = lds_peaks()
+        lds_bytes = bytes_per_edge_iter * edge_iters
+        lds_achieved = lds_bytes / (kernel_ms / 1e3) / 1e9
+        out["roofline"]["lds"] = {"achieved": round(lds_achieved, 1), "unit": "GB/s",
+                                  "peak_read_u8": peaks["read_u8"], "peak_read_b128": peaks["read_b128"],
+                                  "frac_of_u8_peak": round(lds_achieved / peaks["read_u8"], 4),
+                                  "frac_of_b128_peak": round(lds_achieved / peaks["read_b128"], 4),
+                                  "algorithmic_bytes_per_launch": lds_bytes,
+                                  "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration (E and L read and "
+                                                f"written once) x {edge_iters:.0f} edge-iterations",
+                                  "peak_source": "ldpc_probe_lds_bandwidth, measured in this run"}
     if args.pipelined_streams > 1:
         out["pipelined"] = pipelined(gc, code, fr, d_syn, d_llr, wl.max_iter,
                                      (d_bits.cpu().numpy(), conv, iters), args.steps, args.warmup,

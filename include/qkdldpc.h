@@ -298,6 +298,16 @@ int ldpc_oms_backward(const ldpc_code *code, const uint8_t *syndromes, const uin
                       const float *dloss, const void *tape, size_t tape_bytes, float *out_dbeta,
                       float *out_dllr, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Diagnostics: LDS read-bandwidth probe, the measured on-chip peak that the
+ * decoder's LDS traffic is reported against (its state lives in LDS). Launches
+ * n_workgroups workgroups of 1024 threads on the stream; each fills 64 KB of
+ * LDS and every thread then makes reps * 8 conflict-free reads of 16 bytes
+ * (mode 0) or of one byte (mode 1, the width of the decoder's accesses),
+ * folding them into out[workgroup * 1024 + thread] (DEVICE uint32). Bytes read
+ * = n_workgroups * 1024 * reps * 8 * (16 or 1). LDPC_EINVAL for a mode other
+ * than 0 or 1, n_workgroups or reps below 1, or a NULL out. */
+int ldpc_probe_lds_bandwidth(int32_t mode, int32_t n_workgroups, int32_t reps, uint32_t *out, void *stream);
+
 /* Message describing the last error on this thread ("" if none). */
 const char *ldpc_last_error(void);
 

@@ -94,6 +94,8 @@ def lib():
         L.ldpc_batch_destroy.argtypes = [vp]
         L.ldpc_syndrome_batch.restype = C.c_int
         L.ldpc_syndrome_batch.argtypes = [vp, vp, i32, vp, vp]
+        L.ldpc_probe_lds_bandwidth.restype = C.c_int
+        L.ldpc_probe_lds_bandwidth.argtypes = [i32, i32, i32, vp, vp]
         L.ldpc_last_error.restype = C.c_char_p
         L.ldpc_last_error.argtypes = []
         L.ldpc_version.restype = C.c_int
@@ -127,6 +129,14 @@ def header_functions() -> list[str]:
 def _check(rc: int):
     if rc != LDPC_OK:
         raise LdpcError(rc, lib().ldpc_last_error().decode())
+
+
+def ldpc_probe_lds_bandwidth(mode: int, n_workgroups: int, reps: int, out, stream=None):
+    """LDS read-bandwidth probe (mode 0: 16-byte reads, 1: byte reads) into the
+    device uint32 tensor out[n_workgroups * 1024]."""
+    import torch
+    p_out = _dev_ptr(out, torch.int32, (int(n_workgroups) * 1024,), "out")
+    _check(lib().ldpc_probe_lds_bandwidth(int(mode), int(n_workgroups), int(reps), p_out, _stream_ptr(stream)))
 
 
 def ldpc_last_error() -> str:

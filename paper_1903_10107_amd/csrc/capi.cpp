@@ -905,6 +905,18 @@ int ldpc_oms_backward(const ldpc_code *code, const uint8_t *syndromes, const uin
     return LDPC_OK;
 }
 
+int ldpc_probe_lds_bandwidth(int32_t mode, int32_t n_workgroups, int32_t reps, uint32_t *out, void *stream)
+{
+    if (mode != 0 && mode != 1)
+        return fail(LDPC_EINVAL, "ldpc_probe_lds_bandwidth: mode must be 0 or 1");
+    if (n_workgroups < 1 || reps < 1 || !out)
+        return fail(LDPC_EINVAL, "ldpc_probe_lds_bandwidth: n_workgroups and reps must be >= 1, out non-NULL");
+    hipError_t e = qkdldpc::launch_probe_lds(mode, n_workgroups, reps, out, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail("ldpc_probe_lds_bandwidth: kernel launch", e);
+    return LDPC_OK;
+}
+
 const char *ldpc_last_error(void) { return g_err.c_str(); }
 
 int ldpc_version(void) { return 100; }

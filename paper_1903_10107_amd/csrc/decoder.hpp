@@ -61,6 +61,9 @@ hipError_t launch_multi_head(const LaunchPlan &P, const DevCode &C, const Decode
 hipError_t launch_multi_iters(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int t0, int t1,
                               hipStream_t s);
 hipError_t launch_multi_tail(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+// LDS read-bandwidth probe (mode 0: 16-byte reads, 1: byte reads), 1024 threads
+// per workgroup, out[n_workgroups * 1024]
+hipError_t launch_probe_lds(int mode, int n_workgroups, int reps, uint32_t *out, hipStream_t s);
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s);
 hipError_t launch_queue_reset(int *queue, hipStream_t s);
 hipError_t launch_reveal(int8_t *llr, int n, int n_frames, const int32_t *frame_ids, int k, const int32_t *positions,
