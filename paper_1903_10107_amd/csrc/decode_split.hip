@@ -111,10 +111,10 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     int vk = 0;
     int conv, iters = 0;
     const int lp = tid >> 1, np = nthr >> 1;
+    // At most 32 layers (the syndrome bits of a lane's rows fit two registers);
     // global L on this path: every lane pair owns RPL row pairs, and there are
-    // more layers than the prefetch distance; L in LDS: at most 32 layers (the
-    // syndrome bits of a lane's rows fit two registers)
-    if (LG ? hz == RPL * np && C.mb > split_pd<DMAX>() : hz <= RPL * np && C.mb <= 32) {
+    // more layers than the prefetch distance
+    if (C.mb <= 32 && (LG ? hz == RPL * np && C.mb > split_pd<DMAX>() : hz <= RPL * np)) {
         // every row pair has a lane pair: the check is folded into layer 0
         auto unsat_range = [&](int b0, int b1) {
             int u = 0;
@@ -127,28 +127,28 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             return u;
         };
         conv = !block_vote(unsat_range(0, C.mb), flags, vk);
-        if constexpr (!LG) {
-            // Each lane keeps its row pairs' syndrome bits in registers (this path
-            // takes at most 32 layers): word b / 16, bit b % 16 for row b*Z + r and
-            // bit 16 + b % 16 for row b*Z + r + Z/2; layer b's pair (the sign bits
-            // of two 16-bit halves) is then (word << (15 - b % 16)) & 0x80008000.
-            unsigned synm[RPL][2];
+        // Each lane keeps its row pairs' syndrome bits in registers (this path
+        // takes at most 32 layers): word b / 16, bit b % 16 for row b*Z + r and
+        // bit 16 + b % 16 for row b*Z + r + Z/2; layer b's pair (the sign bits
+        // of two 16-bit halves) is then (word << (15 - b % 16)) & 0x80008000.
+        unsigned synm[RPL][2];
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                const int r = lp + k * np;
-                synm[k][0] = synm[k][1] = 0;
-                if (r < hz)
-                    for (int b = 0; b < C.mb; ++b) {
-                        const int i0 = b * z + r, i1 = i0 + hz;
-                        const unsigned bits = (unsigned)((s_syn[i0 >> 3] >> (i0 & 7)) & 1) << (b & 15) |
-                                              (unsigned)((s_syn[i1 >> 3] >> (i1 & 7)) & 1) << (16 + (b & 15));
-                        synm[k][b >> 4] |= bits;
-                    }
-            }
-            auto syn_of = [&](int k, int b) {
-                const unsigned w = b < 16 ? synm[k][0] : synm[k][1];
-                return __builtin_bit_cast(s16x2, (w << (15 - (b & 15))) & 0x80008000u);
-            };
+        for (int k = 0; k < RPL; ++k) {
+            const int r = lp + k * np;
+            synm[k][0] = synm[k][1] = 0;
+            if (r < hz)
+                for (int b = 0; b < C.mb; ++b) {
+                    const int i0 = b * z + r, i1 = i0 + hz;
+                    const unsigned bits = (unsigned)((s_syn[i0 >> 3] >> (i0 & 7)) & 1) << (b & 15) |
+                                          (unsigned)((s_syn[i1 >> 3] >> (i1 & 7)) & 1) << (16 + (b & 15));
+                    synm[k][b >> 4] |= bits;
+                }
+        }
+        auto syn_of = [&](int k, int b) {
+            const unsigned w = b < 16 ? synm[k][0] : synm[k][1];
+            return __builtin_bit_cast(s16x2, (w << (15 - (b & 15))) & 0x80008000u);
+        };
+        if constexpr (!LG) {
             // Each layer step reads its slot addresses and L (private to the lane,
             // written by it one iteration earlier) before the barrier that orders
             // the previous step's E writes, so that after it only E is waited for.
@@ -255,9 +255,15 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                         break;
                     SplitRow<DH> R[RPL];
                     const s16x2 zero = splat2(0);
+                    // slot addresses before the barrier that orders the previous
+                    // step's E writes; after it the E reads
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k)
+                        split_addr<DMIN, DMAX, ET>(R[k], s_tab + b * DH * 2 + h, rr[k], zm);
+                    __syncthreads();
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
-                        split_load_e<DMIN, DMAX, ET>(R[k], s_tab + b * DH * 2 + h, rr[k], zm, hzb);
+                        split_fetch_e<ET>(R[k], hzb);
 #pragma unroll
                         for (int q = 0; q < NW; ++q) {
                             s16x2 lo, hi;
@@ -272,7 +278,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
 #pragma unroll
                         for (int k = 0; k < RPL; ++k) {
                             const s16x2 own = split_e_parity<DMIN, DMAX>(R[k]);
-                            const s16x2 pe = syn_pair(s_syn, rr[k], rr[k] + hz) ^ own ^ swap_pair(own);
+                            const s16x2 pe = syn_of(k, 0) ^ own ^ swap_pair(own);
                             fail0 |= (pe.x | pe.y) < 0;
                         }
                         if (!block_vote(fail0, flags, vk) && !block_vote(unsat_range(1, C.mb), flags, vk)) {
@@ -287,10 +293,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     fetch(pf[j], b + PD >= C.mb ? b + PD - C.mb : b + PD);
 #pragma unroll
                     for (int k = 0; k < RPL; ++k)
-                        split_finish<DMIN, DMAX, ET, RULE, true>(C, R[k], LRef<DH, true>{chunk(b, k)},
-                                                                 syn_pair(s_syn, b * z + rr[k], b * z + rr[k] + hz),
+                        split_finish<DMIN, DMAX, ET, RULE, true>(C, R[k], LRef<DH, true>{chunk(b, k)}, syn_of(k, b),
                                                                  es);
-                    __syncthreads();
                     if (++b == C.mb) {
                         b = 0;
                         iters = t;
@@ -299,6 +303,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     }
                 }
             }
+            // the last step's E writes before the final check and the stage-out
+            __syncthreads();
         }
         if (!conv && A.max_iter > 0)
             conv = !block_vote(unsat_range(0, C.mb), flags, vk);
