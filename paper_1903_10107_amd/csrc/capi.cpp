@@ -393,9 +393,10 @@ qkdldpc::OmsPlan oms_plan(const ldpc_code *c, int32_t n_iter, bool *fits = nullp
     P.threads = (int)std::min<size_t>(1024, round_up(4 * (size_t)h.z, 64));
     const size_t ne = (size_t)h.n_blocks * h.z;
     // reduction scratch, offsets, the block table {column start, shift} with its
-    // alignment, the syndrome
+    // alignment, the syndrome, the target bits
     const size_t fixed = (size_t)16 * P.dmax * sizeof(float) + (size_t)std::max(n_iter, 0) * h.n_blocks * sizeof(float) +
-                         (size_t)h.n_blocks * 8 + 16 + round_up((size_t)(h.m + 7) / 8, 16);
+                         (size_t)h.n_blocks * 8 + 16 + round_up((size_t)(h.m + 7) / 8, 16) +
+                         round_up((size_t)(h.n + 7) / 8, 16);
     const size_t st = ((size_t)h.n + ne) * sizeof(float);
     const size_t limit = (size_t)(c->lds_limit - 1024);
     P.lds_state = st + fixed <= limit;

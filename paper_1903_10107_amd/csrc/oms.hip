@@ -44,9 +44,14 @@ __device__ __forceinline__ float wave_sum(float x)
     return x;
 }
 
-__device__ __forceinline__ float softplus(float u) { return fmaxf(u, 0.f) + log1pf(expf(-fabsf(u))); }
+// softplus(u) = max(u, 0) + log(1 + exp(-|u|)) and the logistic function, on
+// the hardware exp2/log2/reciprocal approximations (about one ulp each): the
+// loss is a sum of positive terms, so the absolute error of log(1 + t) when
+// 1 + t rounds (at most half an ulp of 1 per term) is far below the loss's
+// own rounding; the logistic function feeds gradients only.
+__device__ __forceinline__ float softplus(float u) { return fmaxf(u, 0.f) + __logf(1.f + __expf(-fabsf(u))); }
 
-__device__ __forceinline__ float sigmoid(float u) { return 1.f / (1.f + expf(-u)); }
+__device__ __forceinline__ float sigmoid(float u) { return __builtin_amdgcn_rcpf(1.f + __expf(-u)); }
 
 // +1 for a target bit 0, -1 for 1
 __device__ __forceinline__ float target_sign(const uint8_t *xb, int j) { return (xb[j >> 3] >> (j & 7)) & 1 ? -1.f : 1.f; }
@@ -120,9 +125,11 @@ struct OmsState {
     float *beta;       // offsets [T][n_blocks] staged in LDS
     float *red;        // reduction scratch
     uint8_t *syn;      // packed syndrome of the frame
+    uint8_t *xb;       // packed target bits of the frame (when given)
 };
 
-// LDS: [state if LDS] [block table, 16-byte aligned] [beta T * n_blocks] [red] [syndrome]
+// LDS: [state if LDS] [block table, 16-byte aligned] [beta T * n_blocks] [red] [syndrome,
+// 16-byte padded] [target bits]
 __device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A, bool lds, int red_floats)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -144,6 +151,8 @@ __device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A
     S.red = reinterpret_cast<float *>(p);
     p += (size_t)red_floats * sizeof(float);
     S.syn = p;
+    p += ((size_t)A.syn_bytes + 15) & ~(size_t)15;
+    S.xb = p;
     return S;
 }
 
@@ -153,6 +162,11 @@ __device__ __forceinline__ void stage_common(const DevCode &C, const OmsArgs &A,
     const uint8_t *syn = A.syn + (size_t)blockIdx.x * A.syn_bytes;
     for (int i = tid; i < A.syn_bytes; i += nthr)
         S.syn[i] = syn[i];
+    if (A.xbits) {
+        const uint8_t *xb = A.xbits + (size_t)blockIdx.x * A.bit_bytes;
+        for (int i = tid; i < A.bit_bytes; i += nthr)
+            S.xb[i] = xb[i];
+    }
     for (int i = tid; i < A.n_iter * C.n_blocks; i += nthr)
         S.beta[i] = A.beta[i];
     for (int i = tid; i < C.n_blocks; i += nthr)
@@ -179,7 +193,7 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
         L[e] = 0.f;
     __syncthreads();
     float *tape = A.tape + (size_t)f * T * (ne + n);
-    const uint8_t *xb = A.xbits ? A.xbits + (size_t)f * A.bit_bytes : nullptr;
+    const uint8_t *xb = A.xbits ? S.xb : nullptr;
     float loss = 0.f;
     for (int t = 0; t < T; ++t) {
         const float *bt = S.beta + t * C.n_blocks;
@@ -282,7 +296,7 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
         Lb[e] = 0.f;
     __syncthreads();
     const float *tape = A.tape + (size_t)f * T * (ne + n);
-    const uint8_t *xb = A.xbits + (size_t)f * A.bit_bytes;
+    const uint8_t *xb = S.xb;
     const float g = A.dloss[f] / (float)n;
     // The tape's v of the next row chunk in walk order (layers and iterations in
     // reverse) is requested while the current chunk is processed, so its global
@@ -303,9 +317,22 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
         const float *tv = tape + (size_t)t * (ne + n);
         // the loss term of iteration t
         const float wt = (A.weights ? A.weights[t] : 1.f) * g;
-        for (int j = tid; j < n; j += nthr) {
-            const float y = target_sign(xb, j);
-            Eb[j] += wt * sigmoid(-y * tv[ne + j]) * -y;
+        // four tape reads in flight per thread
+        for (int j0 = tid; j0 < n; j0 += 4 * nthr) {
+            float e4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * nthr;
+                e4[u] = j < n ? tv[ne + j] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * nthr;
+                if (j < n) {
+                    const float y = target_sign(xb, j);
+                    Eb[j] += wt * sigmoid(-y * e4[u]) * -y;
+                }
+            }
         }
         __syncthreads();
         for (int b = C.mb - 1; b >= 0; --b) {
