@@ -186,7 +186,7 @@ def batched(wl, code, n_short, n_frames, steps, warmup):
     fr = I.make_frames(code, n_frames, wl.qber, 10107, n_short=n_short)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     cands = [tune.Schedule("auto", 0, "none", False), tune.Schedule("split", n_cu, "none", False),
-             tune.Schedule("split", 2 * n_cu, "none", False)]
+             tune.Schedule("split", 2 * n_cu, "none", False), tune.Schedule("split", 2 * n_cu, "none", True)]
     best = tune.tune(code.base, code.z, fr.syn, fr.llr, wl.max_iter, acc_bits=wl.acc_bits, cache_path=None,
                      cands=cands, reps=2)
     sched = tune.Schedule(**best["schedule"])
@@ -208,8 +208,9 @@ def ragged(n_frames, steps, warmup):
     """Ragged batch of the rate-adaptive mother code (24x48 base, Z = 2048,
     n = 98304, R = 1/2): each frame's QBER is drawn from {1, 2, 4, 6, 8}% and
     the frame is punctured to its bucket's FER <= 1e-2 operating point; 60
-    iterations. Schedule picked by the autotuner (hardest first = highest QBER
-    first)."""
+    iterations. Schedule picked by the autotuner among one-workgroup-per-frame
+    and persistent launches, direct or replayed from a HIP graph (hardest first
+    = highest QBER first)."""
     import numpy as np
     import torch
     from paper_1903_10107_amd import inputs as I
@@ -221,7 +222,8 @@ def ragged(n_frames, steps, warmup):
     fr = I.make_ragged_frames(code, n_frames, 10107)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     cands = [tune.Schedule("auto", 0, "none", False), tune.Schedule("auto", n_cu, "none", False),
-             tune.Schedule("auto", 2 * n_cu, "none", False), tune.Schedule("auto", 2 * n_cu, "hardest_first", False)]
+             tune.Schedule("auto", 2 * n_cu, "none", False), tune.Schedule("auto", 2 * n_cu, "hardest_first", False),
+             tune.Schedule("auto", 2 * n_cu, "hardest_first", True)]
     best = tune.tune(code.base, code.z, fr.syn, fr.llr, max_iter, difficulty=fr.qber, cache_path=None, cands=cands,
                      reps=2)
     sched = tune.Schedule(**best["schedule"])
