@@ -68,9 +68,7 @@ typedef struct {
                                subtracted from every CN message magnitude at iteration t using
                                row min(t-1, offset_iters-1), result clamped to [0, msg_max];
                                copied at create. NULL = no offsets (the paper's decoder).
-                               Served by the split family with L in LDS and by the pairs, lds
-                               and global families; split_global_l and layer_sync refuse them
-                               (LDPC_EUNSUPPORTED when forced). */
+                               Every kernel family serves them. */
     int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
     int32_t kernel_hint;    /* 0: pick the kernel family automatically; LDPC_HINT_*: use that
                                family, or fail with LDPC_EUNSUPPORTED when it does not apply

@@ -99,19 +99,16 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     const size_t e_al = round_up((size_t)h.n * esize, 16);
 
     // Split (two lanes per row pair): power-of-two Z, forward-backward or min-sum
-    // rule, row degree <= 20 (offset tables only with L in LDS). LDS: E plus a
-    // dummy block column, L as [pair][layer][half][slot][lane] with an odd-dword
-    // pair stride, the
+    // rule, row degree <= 20. LDS: E plus a dummy block column, L as
+    // [pair][layer][half][slot][lane] with an odd-dword pair stride, the
     // syndrome, the lane table, three vote words and the queue slot. When L does
     // not fit, it moves to a global slice per workgroup (mb * Z * DMAX bytes)
     // and only E, the syndrome, the table and the vote words stay in LDS.
     P.split_global_l = false;
     P.layer_sync = false;
     const bool split_hint = hint == LDPC_HINT_SPLIT || hint == LDPC_HINT_SPLIT_GLOBAL_L;
-    // offset tables are served only with L in LDS (the split family proper)
     const bool split_ok = P.pow2 && h.z >= 2 && h.max_deg <= 20 &&
                           (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM);
-    const bool no_off = h.offsets.empty();
     const int dmax = (h.min_deg == 6 && h.max_deg == 6) ? 6 : h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
     if ((hint == 0 || split_hint) && split_ok) {
         const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
@@ -121,7 +118,7 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
         const size_t total_sp = e_sp + l_sp + round_up(syn_bytes, 16) + tab + 16;
         const size_t total_gl = e_sp + round_up(syn_bytes, 16) + tab + 16;
         const bool lds_l = hint != LDPC_HINT_SPLIT_GLOBAL_L && total_sp <= (size_t)lds_limit;
-        const bool glob_l = !lds_l && no_off && hint != LDPC_HINT_SPLIT && total_gl <= (size_t)lds_limit;
+        const bool glob_l = !lds_l && hint != LDPC_HINT_SPLIT && total_gl <= (size_t)lds_limit;
         if (lds_l || glob_l) {
             const size_t l_len = lds_l ? l_sp : 0;
             P.split_dmax = dmax;
@@ -147,7 +144,7 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     // kernel's tables): a global slice per frame holds E (plus the dummy block
     // column) and L in the global-L chunk layout; the frame flags follow the
     // slices in the workspace.
-    if ((hint == 0 || hint == LDPC_HINT_LAYER_SYNC) && split_ok && no_off) {
+    if ((hint == 0 || hint == LDPC_HINT_LAYER_SYNC) && split_ok) {
         P.split_dmax = dmax;
         P.layer_sync = true;
         P.lds_state = false;

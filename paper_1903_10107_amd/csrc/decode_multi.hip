@@ -40,9 +40,11 @@ struct GlobalESink {
 
 // Element indices and values of E for a lane's slots: a0 = ((r + shift) mod Z)
 // + c Z from the lane-table entry {c Z | shift, c Z, pad mask, block}.
-template <int DMIN, int DMAX, typename ET>
+// OFF: also the slots' offsets from the offset table's row off_row (padding
+// slots, block -1, take 0), two 16-bit offsets per register.
+template <int DMIN, int DMAX, typename ET, bool OFF = false>
 __device__ __forceinline__ void load_e_global(SplitRow<DMAX / 2> &R, const int4 *tab, int r, unsigned zm, unsigned hz,
-                                              const ET *__restrict__ E)
+                                              const ET *__restrict__ E, const int32_t *__restrict__ off_row = nullptr)
 {
     constexpr int DH = DMAX / 2;
 #pragma unroll
@@ -55,6 +57,10 @@ __device__ __forceinline__ void load_e_global(SplitRow<DMAX / 2> &R, const int4 
         ev.x = (short)E[a0];
         ev.y = (short)E[a0 ^ hz];
         R.e[i] = ev;
+        if constexpr (OFF) {
+            const unsigned o = (unsigned)(te.w >= 0 ? off_row[te.w] : 0) & 0xffffu;
+            R.off[i / 2] = i % 2 ? R.off[i / 2] | (o << 16) : o;
+        }
     }
 }
 
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(256) void k_multi_finalize(DecodeArgs A, int t)
 }
 
 // Layer b of iteration t for every active frame.
-template <int DMIN, int DMAX, typename ET, int RULE>
+template <int DMIN, int DMAX, typename ET, int RULE, bool OFF>
 __global__ __launch_bounds__(1024) void k_multi_layer(DevCode C, DecodeArgs A, int b, int t)
 {
     constexpr int DH = DMAX / 2;
@@ -191,14 +197,17 @@ __global__ __launch_bounds__(1024) void k_multi_layer(DevCode C, DecodeArgs A, i
     const LRef<DH, true> Lr{reinterpret_cast<uint32_t *>(frame_l(A, f) +
                                                          (((size_t)b * hz + r) * 2 + h) * LRef<DH, true>::BYTES)};
     SplitRow<DH> R;
-    load_e_global<DMIN, DMAX, ET>(R, s_tab + h, r, zm, (unsigned)hz, E);
+    const int32_t *off_row = nullptr;
+    if constexpr (OFF)  // row min(t - 1, offset_iters - 1) of the offset table
+        off_row = C.offsets + (size_t)(t - 1 < C.offset_iters - 1 ? t - 1 : C.offset_iters - 1) * C.n_blocks;
+    load_e_global<DMIN, DMAX, ET, OFF>(R, s_tab + h, r, zm, (unsigned)hz, E, off_row);
     Lr.load(R.lk, t == 1);
     const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
     const int i0 = b * z + r, i1 = i0 + hz;
     s16x2 sp;
     sp.x = (short)(((syn[i0 >> 3] >> (i0 & 7)) & 1) ? -1 : 0);
     sp.y = (short)(((syn[i1 >> 3] >> (i1 & 7)) & 1) ? -1 : 0);
-    split_finish<DMIN, DMAX, ET, RULE, true>(C, R, Lr, sp, GlobalESink<ET>{E, (unsigned)hz});
+    split_finish<DMIN, DMAX, ET, RULE, true, OFF>(C, R, Lr, sp, GlobalESink<ET>{E, (unsigned)hz});
 }
 
 // Hard decisions (wavefront ballots) and, on request, the final state.
@@ -247,7 +256,7 @@ namespace {
 
 // Launch phases: stage-in and the iteration-0 check and retirement (0),
 // iterations t0..t1 (1), stage-out (2).
-template <int DMIN, int DMAX, typename ET, int RULE>
+template <int DMIN, int DMAX, typename ET, int RULE, bool OFF>
 hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
                      hipStream_t s)
 {
@@ -269,7 +278,7 @@ hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A,
     hipError_t e = hipSuccess;
     for (int t = t0; t <= t1 && e == hipSuccess; ++t) {
         for (int b = 0; b < C.mb; ++b)
-            hipLaunchKernelGGL((k_multi_layer<DMIN, DMAX, ET, RULE>), rows, dim3(P.threads), 0, s, C, A, b, t);
+            hipLaunchKernelGGL((k_multi_layer<DMIN, DMAX, ET, RULE, OFF>), rows, dim3(P.threads), 0, s, C, A, b, t);
         hipLaunchKernelGGL((k_multi_check<DMIN, DMAX, ET>), rows, dim3(P.threads), 0, s, C, A);
         hipLaunchKernelGGL(k_multi_finalize, fin, dim3(256), 0, s, A, t);
         e = hipGetLastError();
@@ -281,9 +290,12 @@ template <int DMIN, int DMAX, typename ET>
 hipError_t run_rule(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
                     hipStream_t s)
 {
+    if (C.offsets)
+        return P.cn_rule == LDPC_RULE_MINSUM ? run_multi<DMIN, DMAX, ET, kRuleMinSum, true>(P, C, A, phase, t0, t1, s)
+                                             : run_multi<DMIN, DMAX, ET, kRuleRcbpFB, true>(P, C, A, phase, t0, t1, s);
     if (P.cn_rule == LDPC_RULE_MINSUM)
-        return run_multi<DMIN, DMAX, ET, kRuleMinSum>(P, C, A, phase, t0, t1, s);
-    return run_multi<DMIN, DMAX, ET, kRuleRcbpFB>(P, C, A, phase, t0, t1, s);
+        return run_multi<DMIN, DMAX, ET, kRuleMinSum, false>(P, C, A, phase, t0, t1, s);
+    return run_multi<DMIN, DMAX, ET, kRuleRcbpFB, false>(P, C, A, phase, t0, t1, s);
 }
 
 template <typename ET>

@@ -64,7 +64,6 @@ template <int DMIN, int DMAX, typename ET, int RULE, bool LG, bool OFF>
 __device__ __forceinline__ void split_decode_frame(const DevCode &C, const DecodeArgs &A, const SplitLds<ET> &M,
                                                    uint8_t *Lg, int f)
 {
-    static_assert(!(LG && OFF), "offset tables are served with L in LDS");
     // the offset table's row of iteration t (OFF): min(t - 1, offset_iters - 1)
     auto off_row = [&](int t) -> const int32_t * {
         if constexpr (OFF)
@@ -259,7 +258,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     // step's E writes; after it the E reads
 #pragma unroll
                     for (int k = 0; k < RPL; ++k)
-                        split_addr<DMIN, DMAX, ET>(R[k], s_tab + b * DH * 2 + h, rr[k], zm);
+                        split_addr<DMIN, DMAX, ET, OFF>(R[k], s_tab + b * DH * 2 + h, rr[k], zm, off_row(t));
                     __syncthreads();
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
@@ -293,8 +292,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     fetch(pf[j], b + PD >= C.mb ? b + PD - C.mb : b + PD);
 #pragma unroll
                     for (int k = 0; k < RPL; ++k)
-                        split_finish<DMIN, DMAX, ET, RULE, true>(C, R[k], LRef<DH, true>{chunk(b, k)}, syn_of(k, b),
-                                                                 es);
+                        split_finish<DMIN, DMAX, ET, RULE, true, OFF>(C, R[k], LRef<DH, true>{chunk(b, k)},
+                                                                      syn_of(k, b), es);
                     if (++b == C.mb) {
                         b = 0;
                         iters = t;
@@ -514,6 +513,9 @@ hipError_t launch_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs 
 
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
+    if (P.split_global_l && C.offsets)
+        return P.acc_bits == 16 ? launch_split<int16_t, true, true>(P, C, A, s)
+                                : launch_split<int8_t, true, true>(P, C, A, s);
     if (P.split_global_l)
         return P.acc_bits == 16 ? launch_split<int16_t, true, false>(P, C, A, s)
                                 : launch_split<int8_t, true, false>(P, C, A, s);

@@ -72,6 +72,10 @@ CASES = {
                                 {"kernel": "layer_sync", "cn_rule": 2, "acc_bits": 16}, {}),
     "layer_sync_deg6_ragged": (lambda: I.make_base(24, 48, 256), 256, 6, 0.04, 30, {"kernel": "layer_sync"},
                                {"short_frac": 0.05, "punct_frac": 0.1}),
+    "deg6_n98304_global_l_offsets": (lambda: I.make_base(24, 48, 2048), 2048, 2, 0.04, 12,
+                                     {"cn_rule": 2, "offsets": "rand_signed"}, {"short_frac": 0.1, "punct_frac": 0.1}),
+    "layer_sync_offsets": (lambda: I.make_base(5, 32, 64), 64, 6, 0.02, 30,
+                           {"kernel": "layer_sync", "offsets": "rand_signed"}, {}),
     "max_iter0": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 0, {}, {}),
     "zero_error": (lambda: I.make_base(5, 32, 32), 32, 8, 1e-9, 50, {}, {}),
     "row_deg_24": (lambda: _rand_base(2, 24, 64, 7, 2), 64, 8, 0.01, 30, {}, {}),
