@@ -33,8 +33,14 @@ struct GlobalESink {
     unsigned hz;  // Z/2: flips between the two rows' columns
     __device__ __forceinline__ void operator()(unsigned a0, s16x2 o) const
     {
-        E[a0] = (ET)o.x;
-        E[a0 ^ hz] = (ET)o.y;
+        at(a0) = (ET)o.x;
+        at(a0 ^ hz) = (ET)o.y;
+    }
+    // element i through a 32-bit byte offset from the frame's (uniform) base, so
+    // the access takes the scalar-base plus vector-offset form
+    __device__ __forceinline__ ET &at(unsigned i) const
+    {
+        return *reinterpret_cast<ET *>(reinterpret_cast<uint8_t *>(E) + (i * (unsigned)sizeof(ET)));
     }
 };
 
@@ -53,10 +59,9 @@ __device__ __forceinline__ void load_e_global(SplitRow<DMAX / 2> &R, const int4 
         const unsigned a0 = (((unsigned)r + (unsigned)te.x) & zm) | (unsigned)te.y;
         R.a0[i] = a0;
         R.pm[i] = te.z;
-        s16x2 ev;
-        ev.x = (short)E[a0];
-        ev.y = (short)E[a0 ^ hz];
-        R.e[i] = ev;
+        const uint8_t *eb = reinterpret_cast<const uint8_t *>(E);  // 32-bit byte offsets, uniform base
+        R.e[i] = pack_halves(*reinterpret_cast<const ET *>(eb + a0 * (unsigned)sizeof(ET)),
+                             *reinterpret_cast<const ET *>(eb + (a0 ^ hz) * (unsigned)sizeof(ET)));
         if constexpr (OFF) {
             const unsigned o = (unsigned)(te.w >= 0 ? off_row[te.w] : 0) & 0xffffu;
             R.off[i / 2] = i % 2 ? R.off[i / 2] | (o << 16) : o;

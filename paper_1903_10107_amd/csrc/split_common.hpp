@@ -313,10 +313,13 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
             const s16x2 g = R.e[i] - vmin2(vmax2(R.e[i], -em1), em1);
             o = vmin2(vmax2(v[i] + (g * splat2(511) + ln[i]), -em), em);
         } else {
-            const s16x2 ne = vmin2(vmax2(__builtin_elementwise_add_sat(v[i], ln[i]), -em), em);
-            const s16x2 ae = vmax2(R.e[i], -R.e[i]);
-            const s16x2 frozen = vmin2(em - ae, splat2(1)) - splat2(1);
-            o = (frozen & R.e[i]) | (~frozen & ne);
+            // 16-bit E: the same g, scaled to +-32767 and added with saturation
+            // after the update. A frozen E = E_max gives v >= E_max - MSG_max, so
+            // v + ln >= E_max - 2 MSG_max and the saturating sum reaches at least
+            // min(32767, E_max + 32513) >= E_max; symmetrically for -E_max.
+            const s16x2 g = R.e[i] - vmin2(vmax2(R.e[i], -em1), em1);
+            const s16x2 x = __builtin_elementwise_add_sat(v[i], ln[i]);
+            o = vmin2(vmax2(__builtin_elementwise_add_sat(x, g * splat2(32767)), -em), em);
         }
         es(R.a0[i], o);
     }
