@@ -48,6 +48,13 @@ CASES = {
     "z1500_rows_per_thread_2": (lambda: _rand_base(3, 8, 1500, 6), 1500, 4, 0.03, 30, {}, {}),
     "acc16": (lambda: I.make_base(5, 32, 256), 256, 8, 0.02, 30, {"acc_bits": 16}, {}),
     "acc8_emax100": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30, {"e_max": 100}, {}),
+    # 16-bit soft values with a low E_max: the Alg. 2 freeze fires often
+    "acc16_emax80": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30, {"acc_bits": 16, "e_max": 80},
+                     {"short_frac": 0.2}),
+    "layer_sync_acc16_emax80": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30,
+                                {"kernel": "layer_sync", "acc_bits": 16, "e_max": 80}, {"short_frac": 0.2}),
+    "acc8_emax40_frozen": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30, {"e_max": 40}, {"short_frac": 0.2}),
+    "acc16_emax1": (lambda: I.make_base(5, 32, 32), 32, 8, 0.02, 10, {"acc_bits": 16, "e_max": 1}, {}),
     "msgmax31": (lambda: I.make_base(5, 32, 64), 64, 8, 0.02, 30, {"msg_max": 31}, {}),
     "rule_eq7": (lambda: I.make_base(5, 32, 32), 32, 16, 0.02, 30, {"cn_rule": 1}, {}),
     "rule_minsum": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 30, {"cn_rule": 2}, {}),
