@@ -369,6 +369,45 @@ def retry_figure(n_frames, extra=2048, step=512, max_rounds=12):
     return out
 
 
+def syndrome_figure(n_frames, steps, warmup):
+    """Alice's side (s = H x, ldpc_syndrome_batch) on n_frames random frames of
+    the headline code (n = 32768) and on the 32 frames of the n = 2^20 code:
+    encoded key bits per second and the HBM-equivalent fraction (packed bits in,
+    packed syndrome out). The first frames are checked against the CPU
+    generator's syndromes."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+    from paper_1903_10107_amd import inputs as I
+
+    out = {}
+    for name, (mb, nb, z, F) in (("n32768", (5, 32, 1024, n_frames)), ("n1048576", (10, 64, 16384, 32))):
+        code = I.Code(I.make_base(mb, nb, z), z)
+        gc = B.Code(code.base, code.z)
+        rng = np.random.default_rng(1903)
+        x = rng.integers(0, 2, size=(F, code.n), dtype=np.uint8)
+        xb = torch.from_numpy(I.pack_bits(x)).cuda()
+        syn = torch.zeros((F, (code.m + 7) // 8), dtype=torch.uint8, device="cuda")
+        for _ in range(max(1, warmup)):
+            B.ldpc_syndrome_batch(gc, xb, F, syn)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(5, steps)
+        a.record()
+        for _ in range(reps):
+            B.ldpc_syndrome_batch(gc, xb, F, syn)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        ref = I.pack_bits(I.syndrome_bits(code, x[:2]))
+        assert np.array_equal(syn[:2].cpu().numpy(), ref), "syndrome encoder disagrees with the generator"
+        io = F * ((code.n + 7) // 8 + (code.m + 7) // 8)
+        out[name] = {"frames": F, "ms_per_launch": round(ms, 4),
+                     "gbit_s_encoded": round(F * code.n / (ms / 1e3) / 1e9, 1),
+                     "hbm_equivalent_frac": round(io / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def lds_peaks(reps: int = 256, n_wg: int = 2048) -> dict:
     """Measured LDS read bandwidth of the whole chip (GB/s) for 16-byte and for
     byte reads (ldpc_probe_lds_bandwidth: conflict-free reads, 1024-thread
@@ -492,6 +531,8 @@ def main():
     ap.add_argument("--retry-frames", type=int, default=2048,
                     help="frames of the reveal-and-retry figure on the ragged batch (0: skip)")
     ap.add_argument("--no-large", action="store_true", help="skip the n = 1048576 figure")
+    ap.add_argument("--syndrome-frames", type=int, default=4096,
+                    help="frames of the syndrome-encoder figure (Alice's side; 0: skip)")
     ap.add_argument("--pipelined-streams", type=int, default=3,
                     help="streams for the pipelined figure (consecutive batches overlapped; < 2: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -655,6 +696,8 @@ def main():
         out["learned"] = learned(args.learned_steps, args.steps, args.warmup)
     if args.retry_frames:
         out["retry"] = retry_figure(args.retry_frames)
+    if args.syndrome_frames:
+        out["syndrome"] = syndrome_figure(args.syndrome_frames, args.steps, args.warmup)
     if not args.no_large:
         out["large"] = large_frames(args.steps, args.warmup)
     if not args.no_cpu_baseline:

@@ -33,9 +33,61 @@ __global__ __launch_bounds__(256) void k_syndrome(DevCode C, const uint8_t *__re
     }
 }
 
+// The same with the frame's packed bits staged in LDS first (one workgroup of
+// 1024 threads per frame; every check row then reads its d bits from LDS), for
+// batches of many frames whose packed frame (n / 8 bytes) fits in LDS.
+__global__ __launch_bounds__(1024) void k_syndrome_lds(DevCode C, const uint8_t *__restrict__ bits, int bit_bytes,
+                                                       uint8_t *__restrict__ out_syn, int syn_bytes)
+{
+    extern __shared__ __align__(16) uint8_t s_x[];
+    const int f = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+    const uint8_t *x = bits + (size_t)f * bit_bytes;
+    for (int i = tid; i < bit_bytes; i += nthr)
+        s_x[i] = x[i];
+    __syncthreads();
+    const int lane = tid & 63;
+    // rows in whole waves, so that every ballot covers 64 consecutive rows
+    for (int i0 = tid - lane; i0 < C.m; i0 += nthr) {
+        const int i = i0 + lane;
+        int par = 0;
+        if (i < C.m) {
+            const int b = i / C.z, r = i - b * C.z;
+            const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
+            for (int k = 0; k < d; ++k) {
+                const int j = ldc(C.colbase, o + k) + rot(r, ldc(C.shift, o + k), C.z);
+                par ^= (s_x[j >> 3] >> (j & 7)) & 1;
+            }
+        }
+        const unsigned long long mask = __ballot(par);
+        if (lane < 8) {
+            const int byte = (i0 >> 3) + lane;
+            if (byte < syn_bytes)
+                out_syn[(size_t)f * syn_bytes + byte] = (uint8_t)(mask >> (8 * lane));
+        }
+    }
+}
+
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s)
 {
     const int bit_bytes = (C.n + 7) / 8, syn_bytes = (C.m + 7) / 8;
+    int dev = 0, lds_limit = 0;
+    hipError_t e0 = hipGetDevice(&dev);
+    if (e0 == hipSuccess)
+        e0 = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e0 != hipSuccess)
+        return e0;
+    // one workgroup per frame fills the chip only with many frames; a few long
+    // frames go row-parallel instead
+    if (bit_bytes <= lds_limit && n_frames >= 128) {
+        if (bit_bytes > 65536) {
+            hipError_t e = allow_max_lds<k_syndrome_lds>();
+            if (e != hipSuccess)
+                return e;
+        }
+        hipLaunchKernelGGL(k_syndrome_lds, dim3(n_frames), dim3(1024), bit_bytes, s, C, bits, bit_bytes, out_syn,
+                           syn_bytes);
+        return hipGetLastError();
+    }
     const int threads = 256;
     dim3 grid((C.m + threads - 1) / threads, n_frames);
     hipLaunchKernelGGL(k_syndrome, grid, dim3(threads), 0, s, C, bits, bit_bytes, out_syn, syn_bytes);
