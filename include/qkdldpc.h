@@ -145,7 +145,8 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
  * LDPC_KERNEL_LAYER_SYNC  one launch per layer over all frames, several
  *                      workgroups per frame, E and L in global slices per frame
  *                      (codes whose soft values do not fit in LDS, e.g. n = 2^20);
- *                      the decode is a sequence of launches on the stream.
+ *                      the decode is a sequence of launches on the stream; at
+ *                      most 65535 frames per decode call (LDPC_EINVAL above).
  * Automatic selection prefers them in the order SPLIT, SPLIT_GLOBAL_L,
  * LAYER_SYNC, PAIRS, LDS, GLOBAL, taking the first that applies. Also the
  * workgroup size and the dynamic LDS bytes per workgroup. Any output pointer may

@@ -244,6 +244,9 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
         return fail(LDPC_EINVAL, "ldpc_decode_batch: max_iter < 0");
     if (n_frames > 0 && (!syndromes || !llr_in || !out_bits || !out_converged))
         return fail(LDPC_EINVAL, "ldpc_decode_batch: syndromes, llr_in, out_bits and out_converged must be non-NULL");
+    // the layer-synchronous launches put the frame index in the second grid dimension
+    if (code->plan.layer_sync && n_frames > 65535)
+        return fail(LDPC_EINVAL, "ldpc_decode_batch: the layer-synchronous family takes at most 65535 frames per call");
     if (sched) {
         if (sched->persistent_workgroups < 0)
             return fail(LDPC_EINVAL, "ldpc_schedule: persistent_workgroups < 0");

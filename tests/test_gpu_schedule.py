@@ -233,3 +233,18 @@ def test_early_stop_all_converged_at_iteration_0_and_argument_errors(B):
     B.ldpc_decode_batch_sched(sp, syn, llr, 4, 20, bits, conv, iters, check_every=2)
     torch.cuda.synchronize()
     assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+
+
+def test_layer_sync_frame_limit_is_an_argument_error(B):
+    """The layer-synchronous launches index frames in the second grid dimension:
+    more than 65535 frames per call is refused before anything is launched."""
+    import torch
+    code = I.Code(I.make_base(5, 32, 32), 32)
+    gc = B.Code(code.base, code.z, kernel="layer_sync")
+    F = 65536
+    syn = torch.zeros((F, (code.m + 7) // 8), dtype=torch.uint8, device="cuda")
+    llr = torch.zeros((F, code.n), dtype=torch.int8, device="cuda")
+    bits, conv, iters = _outs(code, F)
+    with pytest.raises(B.LdpcError) as ei:
+        B.ldpc_decode_batch_sched(gc, syn, llr, F, 10, bits, conv, iters)
+    assert ei.value.code == B.LDPC_EINVAL
