@@ -168,3 +168,38 @@ def test_oms_argument_errors(B):
     assert lib.ldpc_oms_backward(code.handle, t.data_ptr(), None, 1, 2, t.data_ptr(), None, t.data_ptr(),
                                  t.data_ptr(), 1 << 30, t.data_ptr(), None, t.data_ptr(), 1 << 30,
                                  None) == B.LDPC_EINVAL                                      # target NULL
+
+
+def test_full_training_configuration_sampled(B):
+    """The training workload as the benchmark runs it (n = 8192, 5x32 base with
+    Z = 256, 512 frames per launch, 20 iterations, 36% shortened, the integer
+    decoder's LLR grid): frames 0 and 511 against the FP64 oracle. Only those
+    two frames carry a loss weight, so the summed offset gradient is theirs.
+    Without saturation the soft values of a converging frame grow by orders of
+    magnitude over 20 iterations (frame 511 reaches about 6e6), past the range
+    where FP32 holds every multiple of 1/128, so E is compared to a relative
+    1e-6 (frame 0 stays small and matches exactly)."""
+    from paper_1903_10107_amd import learn
+    code = I.Code(I.make_base(5, 32, 256), 256)
+    F, T = 512, 20
+    fr = I.make_frames(code, F, 0.02, 4242, n_short=int(0.36 * code.n))
+    llr = learn.training_llr(fr).astype(np.float64)           # integer LLRs x 5/16: exact in FP32
+    rng = np.random.default_rng(9)
+    beta = (2 * np.floor(rng.uniform(0.0, 0.6, size=(T, code.n_blocks)) * 64) + 1) / 128
+    weights = np.linspace(0.5, 1.5, T)
+    dloss = np.zeros(F)
+    dloss[[0, F - 1]] = [1.0, 0.75]
+    _say(f"[gpu oms] full training configuration n={code.n} F={F} T={T}")
+    loss, E, db, dl = _gpu_loss_grad(B, code.base, code.z, fr, llr, beta, weights, dloss, T)
+    sel = [0, F - 1]
+    syn = oms.unpack_syndrome(fr.syn[sel], code.m)
+    w32 = weights.astype(np.float32)
+    ref = oms.oms_grad(code.base, code.z, syn, llr[sel], beta, fr.x[sel], w32, dloss[sel].astype(np.float32))
+    _, Eref, _ = oms.oms_forward(code.base, code.z, syn, llr[sel], beta, fr.x[sel], w32)
+    Eref = Eref.numpy()
+    assert np.array_equal(E[0], Eref[0].astype(np.float32)), "small soft values: the forward pass is exact"
+    assert np.allclose(E[sel], Eref, rtol=1e-6, atol=0)
+    assert np.allclose(loss[sel], ref["loss"], rtol=1e-4, atol=1e-6)
+    assert np.allclose(db, ref["dbeta"], rtol=1e-3, atol=1e-3 * np.abs(ref["dbeta"]).max())
+    assert np.allclose(dl[sel], ref["dllr"], rtol=1e-3, atol=1e-3 * np.abs(ref["dllr"]).max())
+    assert not np.any(dl[1:F - 1]), "frames without a loss weight get no gradient"
