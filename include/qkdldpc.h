@@ -209,7 +209,9 @@ size_t ldpc_workspace_bytes_sched(const ldpc_code *code, int32_t n_frames, const
  * retired (it waits for the stream after each block). All
  * pointers are DEVICE pointers that must stay valid for the life of the batch;
  * the workspace, when one is needed and not given, is allocated at create and
- * freed at destroy. The code handle must outlive the batch. */
+ * freed at destroy. The code handle must outlive the batch. A batch owns fixed
+ * output and workspace buffers, so two launches of the same batch must not
+ * overlap (launch it on one stream, or order the streams). */
 typedef struct ldpc_batch ldpc_batch;
 int ldpc_batch_create(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
                       int32_t n_frames, int32_t max_iter, uint8_t *out_bits, uint8_t *out_converged,
