@@ -37,6 +37,10 @@ def _rand_base(mb, nb, z, seed, col_weight=3):
     return I.make_base(mb, nb, z, col_weight, seed)
 
 
+_HAMMING = np.array([[0, 0, 0, -1, 0, -1, -1],
+                     [0, 0, -1, 0, -1, 0, -1],
+                     [0, -1, 0, 0, -1, -1, 0]], dtype=np.int32)
+
 CASES = {
     # name: (base factory, z, frames, qber, max_iter, kwargs for code, frame kwargs)
     "n1024_q1": (lambda: I.make_base(5, 32, 32), 32, 64, 0.01, 50, {}, {}),
@@ -86,6 +90,10 @@ CASES = {
     "max_iter0": (lambda: I.make_base(5, 32, 32), 32, 16, 0.01, 0, {}, {}),
     "zero_error": (lambda: I.make_base(5, 32, 32), 32, 8, 1e-9, 50, {}, {}),
     "row_deg_24": (lambda: _rand_base(2, 24, 64, 7, 2), 64, 8, 0.01, 30, {}, {}),
+    # Z = 1: a plain (Hamming (7,4)) parity-check matrix written as a base matrix,
+    # and its Z = 2 lift
+    "z1_hamming": (lambda: _HAMMING, 1, 16, 0.1, 10, {}, {}),
+    "z2_hamming_lift": (lambda: _HAMMING, 2, 16, 0.1, 10, {}, {}),
 }
 
 
