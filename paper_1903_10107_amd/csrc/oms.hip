@@ -453,16 +453,42 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
             A.dllr[(size_t)f * n + j] = Eb[j];
 }
 
-// dbeta[q] = sum over frames of dbeta_frames[f][q], in frame order
-__global__ void k_oms_sum_frames(const float *__restrict__ part, int n_frames, int per_frame, float *__restrict__ out)
+// dbeta[q] = sum over frames of dbeta_frames[f][q] in a fixed order: the
+// frames split into kSumGroups contiguous groups, each summed in frame order by
+// its own lane (loads eight at a time), then the group sums in group order, so
+// the result is the same on every run.
+constexpr int kSumGroups = 8, kSumCols = 32;
+__global__ __launch_bounds__(kSumGroups * kSumCols) void k_oms_sum_frames(const float *__restrict__ part, int n_frames,
+                                                                        int per_frame, float *__restrict__ out)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= per_frame)
-        return;
+    __shared__ float partial[kSumGroups][kSumCols];
+    const int c = threadIdx.x % kSumCols, g = threadIdx.x / kSumCols;
+    const int q = blockIdx.x * kSumCols + c;
+    const int per_group = (n_frames + kSumGroups - 1) / kSumGroups;
+    const int f0 = g * per_group, f1 = min(n_frames, f0 + per_group);
     float s = 0.f;
-    for (int f = 0; f < n_frames; ++f)
-        s += part[(size_t)f * per_frame + q];
-    out[q] = s;
+    if (q < per_frame) {
+        int f = f0;
+        for (; f + 8 <= f1; f += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = part[(size_t)(f + u) * per_frame + q];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                s += v[u];
+        }
+        for (; f < f1; ++f)
+            s += part[(size_t)f * per_frame + q];
+    }
+    partial[g][c] = s;
+    __syncthreads();
+    if (g == 0 && q < per_frame) {
+        float t = 0.f;
+        for (int i = 0; i < kSumGroups; ++i)
+            t += partial[i][c];
+        out[q] = t;
+    }
 }
 
 namespace {
@@ -512,7 +538,8 @@ hipError_t bwd(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t
     if (e != hipSuccess)
         return e;
     const int per = A.n_iter * C.n_blocks;
-    hipLaunchKernelGGL(k_oms_sum_frames, dim3((per + 255) / 256), dim3(256), 0, s, A.dbeta_frames, A.n_frames, per,
+    hipLaunchKernelGGL(k_oms_sum_frames, dim3((per + kSumCols - 1) / kSumCols), dim3(kSumGroups * kSumCols), 0, s,
+                       A.dbeta_frames, A.n_frames, per,
                        A.dbeta);
     return hipGetLastError();
 }
