@@ -412,6 +412,52 @@ def syndrome_figure(n_frames, steps, warmup):
     return out
 
 
+def end_to_end(gc, code, fr, max_iter, key_bits_ok, steps, warmup):
+    """The headline step with the host link included: the batch's LLRs and
+    syndromes copied from pinned host memory, the decode, and the packed bits,
+    flags and counts copied back, all on one stream, timed with HIP events
+    around each step (the PCIe-inclusive rate; `value` excludes the copies)."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+
+    F = fr.n_frames
+    h_syn = torch.from_numpy(fr.syn).pin_memory()
+    h_llr = torch.from_numpy(fr.llr).pin_memory()
+    h_bits = torch.empty((F, (code.n + 7) // 8), dtype=torch.uint8).pin_memory()
+    h_conv = torch.empty(F, dtype=torch.uint8).pin_memory()
+    h_iters = torch.empty(F, dtype=torch.int32).pin_memory()
+    d_syn, d_llr = torch.empty_like(h_syn, device="cuda"), torch.empty_like(h_llr, device="cuda")
+    d_bits, d_conv, d_iters = (torch.empty_like(h_bits, device="cuda"), torch.empty_like(h_conv, device="cuda"),
+                               torch.empty_like(h_iters, device="cuda"))
+
+    def step():
+        d_syn.copy_(h_syn, non_blocking=True)
+        d_llr.copy_(h_llr, non_blocking=True)
+        B.ldpc_decode_batch_ex(gc, d_syn, d_llr, F, max_iter, d_bits, d_conv, d_iters)
+        h_bits.copy_(d_bits, non_blocking=True)
+        h_conv.copy_(d_conv, non_blocking=True)
+        h_iters.copy_(d_iters, non_blocking=True)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    h2d = h_syn.numel() + h_llr.numel()
+    d2h = h_bits.numel() + h_conv.numel() + 4 * h_iters.numel()
+    return {"ms_per_step": round(ms, 4), "value": round(key_bits_ok / (ms / 1e3) / 1e6, 2), "unit": "Mbit/s",
+            "h2d_bytes": int(h2d), "d2h_bytes": int(d2h), "timing": "median over steps of HIP events around "
+            "copy in, decode, copy out on one stream (pinned host buffers)"}
+
+
 def lds_peaks(reps: int = 256, n_wg: int = 2048) -> dict:
     """Measured LDS read bandwidth of the whole chip (GB/s) for 16-byte and for
     byte reads (ldpc_probe_lds_bandwidth: conflict-free reads, 1024-thread
@@ -688,6 +734,8 @@ def main():
                                   "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration (E and L read and "
                                                 f"written once) x {edge_iters:.0f} edge-iterations",
                                   "peak_source": "ldpc_probe_lds_bandwidth, measured in this run"}
+    out["end_to_end"] = end_to_end(gc, code, fr, wl.max_iter, float(key_bits[correct].sum()),
+                                   max(10, args.steps // 5), max(1, args.warmup))
     if args.pipelined_streams > 1:
         out["pipelined"] = pipelined(gc, code, fr, d_syn, d_llr, wl.max_iter,
                                      (d_bits.cpu().numpy(), conv, iters), args.steps, args.warmup,
