@@ -89,6 +89,35 @@ def measured_traffic(workload: str):
         return None
 
 
+def cpu_baseline_large(seconds: float):
+    """The oracle on the n = 2^20 workload (10x64 base, Z = 16384, 16-bit soft
+    values, QBER 2% unshortened, 80 iterations: every frame runs all of them), a
+    bounded sample of frames, one per thread: frame-iterations per second, the
+    unit the GPU figure reports beside it."""
+    import numpy as np
+    import oracle as O
+    from paper_1903_10107_amd import inputs as I
+
+    wl = I.WORKLOADS["n1048576_q2"]
+    code = wl.code()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    threads = max(1, min(threads, O.max_threads()))
+    fr = I.make_frames(code, threads, wl.qber, 10107)
+    # a shorter iteration limit keeps the sample bounded (QBER 2% unshortened runs
+    # every iteration, so the work per iteration is fixed): two iterations
+    # calibrate the count that fills the requested time
+    t = time.perf_counter()
+    O.decode(code.base, code.z, fr.syn, fr.llr, 2, acc_bits=wl.acc_bits, n_threads=threads)
+    it = max(2, min(wl.max_iter, int(2 * seconds / max(time.perf_counter() - t, 1e-3))))
+    t = time.perf_counter()
+    r = O.decode(code.base, code.z, fr.syn, fr.llr, it, acc_bits=wl.acc_bits, n_threads=threads)
+    el = time.perf_counter() - t
+    fi = float(np.sum(r["iters"]))
+    return {"frame_iterations_per_s": round(fi / el, 2), "cores": threads, "kind": "oracle",
+            "sample": f"{threads} frames of n = {code.n}, {it} iterations each ({fi:.0f} frame-iterations, "
+                      f"{el:.1f} s, one frame per OpenMP thread)"}
+
+
 def cpu_baseline(code, fr, wl, seconds: float):
     import numpy as np
     import oracle as O
@@ -754,6 +783,8 @@ def main():
         out["large"] = large_frames(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
+        if not args.no_large:
+            out["cpu_baseline"]["large"] = cpu_baseline_large(args.cpu_seconds / 3)
     print(json.dumps(out), flush=True)
 
 
