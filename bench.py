@@ -345,6 +345,8 @@ def learned(steps_train, steps, warmup):
     # is a fused multiply-add and packed FP32 is not used, so the ALU peak is one
     # 32-bit op per lane per cycle: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T/s.
     fwd_tops = 14 * edge_iters / (fwd_ms / 1e3) / 1e12
+    # FP32 state per edge-iteration: L read and written, E read and written (16 B)
+    fwd_gbs = 16 * edge_iters / (fwd_ms / 1e3) / 1e9
 
     offsets = LN.int_offsets(bt.cpu().numpy())
     judged = {}
@@ -368,7 +370,11 @@ def learned(steps_train, steps, warmup):
             "forward_roofline": {"bound": "alu", "achieved": round(fwd_tops, 3), "peak": FP32_ALU_PEAK_TOPS,
                                  "unit": "TOP/s", "frac": round(fwd_tops / FP32_ALU_PEAK_TOPS, 4),
                                  "unit_ops": f"14 FP32 ops per edge-iteration x {edge_iters:.0f} edge-iterations",
-                                 "fp32_vector_peak_tflops": 157.3},
+                                 "fp32_vector_peak_tflops": 157.3,
+                                 "hbm_equivalent": {"achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS,
+                                                    "unit": "GB/s", "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
+                                                    "unit_bytes": "16 B per edge-iteration (FP32 L and E, "
+                                                                  "each read and written once)"}},
             "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "judged": judged}
 
 
@@ -621,6 +627,8 @@ def main():
     ap.add_argument("--qber-sweep", default="",
                     help="comma-separated QBERs for --fer-sweep (default: the workload's)")
     ap.add_argument("--sweep-frames", type=int, default=4096)
+    ap.add_argument("--only", choices=("learned", "syndrome", "retry", "large"), default=None,
+                    help="run one figure alone and print it as one JSON line (for profiling its kernels)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="instead of decoding, run a plain device copy of BYTES bytes per step "
                          "(reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -638,6 +646,14 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, args.steps, args.warmup)
+        return
+    if args.only:
+        torch.cuda.set_device(0)
+        fig = {"learned": lambda: learned(args.learned_steps, args.steps, args.warmup),
+               "syndrome": lambda: syndrome_figure(args.syndrome_frames, args.steps, args.warmup),
+               "retry": lambda: retry_figure(args.retry_frames),
+               "large": lambda: large_frames(args.steps, args.warmup)}[args.only]()
+        print(json.dumps({"figure": args.only, args.only: fig}), flush=True)
         return
     if args.workload == "n98304_ragged":
         # the ragged rate-adaptive batch alone (for profiling its kernel)

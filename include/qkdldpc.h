@@ -270,14 +270,15 @@ int ldpc_reveal_batch(const ldpc_code *code, int8_t *llr, int32_t n_frames, cons
  *   target_bits   uint8 [F][ceil(n/8)] the transmitted words x, packed LSB-first
  *   beta          float [n_iter][n_blocks] (blocks in row-major base-matrix order)
  *   loss_weights  float [n_iter], or NULL for all ones
- *   tape          ldpc_oms_tape_bytes(code, F, n_iter) bytes: written by the
- *                 forward pass, read by the backward pass (VN->CN values of
- *                 every edge and iteration, soft values after every iteration)
+ *   tape          ldpc_oms_tape_bytes(code, F, n_iter) bytes, 16-byte aligned:
+ *                 written by the forward pass, read by the backward pass (per
+ *                 check row and iteration the two smallest |VN->CN| values, their
+ *                 edge indices and the signs; soft values after every iteration)
  *   workspace     ldpc_oms_workspace_bytes(code, F, n_iter) bytes (may be NULL
  *                 when that is 0 for the forward pass): FP32 state of codes whose
  *                 state does not fit in LDS, and per-frame offset gradients
- * Returns LDPC_EINVAL for bad arguments (n_iter < 1, NULL pointers, short tape
- * or workspace), LDPC_EUNSUPPORTED when the offset table (n_iter x n_blocks
+ * Returns LDPC_EINVAL for bad arguments (n_iter < 1, NULL pointers, short or
+ * misaligned tape, short workspace), LDPC_EUNSUPPORTED when the offset table (n_iter x n_blocks
  * floats) does not fit in on-chip memory, LDPC_EDEVICE for launch failures.
  * Asynchronous on stream.
  * ------------------------------------------------------------------------ */

@@ -408,7 +408,8 @@ qkdldpc::OmsPlan oms_plan(const ldpc_code *c, int32_t n_iter, bool *fits = nullp
 
 size_t oms_tape_floats(const HostCode &h, int32_t n_iter)
 {
-    return (size_t)n_iter * ((size_t)h.n_blocks * h.z + h.n);
+    // per iteration: a four-word record per check row, then E
+    return (size_t)n_iter * ((size_t)4 * h.m + (((size_t)h.n + 3) & ~(size_t)3));
 }
 
 size_t oms_state_bytes(const ldpc_code *c, const qkdldpc::OmsPlan &P, int32_t n_frames)
@@ -434,6 +435,8 @@ int oms_check(const ldpc_code *code, const char *who, const uint8_t *syndromes, 
         return fail(LDPC_EINVAL, w + ": syndromes and tape must be non-NULL");
     if (tape_bytes < oms_tape_floats(code->h, n_iter) * sizeof(float) * (size_t)n_frames)
         return fail(LDPC_EINVAL, w + ": tape smaller than ldpc_oms_tape_bytes");
+    if (n_frames > 0 && reinterpret_cast<uintptr_t>(tape) % 16 != 0)
+        return fail(LDPC_EINVAL, w + ": tape must be 16-byte aligned");
     bool fits = false;
     (void)oms_plan(code, n_iter, &fits);
     if (!fits)

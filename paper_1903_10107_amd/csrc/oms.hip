@@ -10,19 +10,22 @@
 //   sigma_k = (-1)^{s_i} prod_k' sgn(v_k') sgn(v_k), sgn(0) = +1
 //   L_k = sigma_k max(min_{k' != k} |v_k'| - beta_{t, blk_k}, 0),  E_{j_k} = v_k + L_k
 // and after iteration t the loss gains w_t / n * sum_j softplus(-(1 - 2 x_j) E_j).
-// The tape keeps every v_k and E after every iteration; the backward pass walks
-// layers and iterations in reverse, recomputes the minima and their indices from
-// v, and propagates the adjoints of E and L. Ties go to the lowest edge index,
-// d|v|/dv is 0 at v = 0 and the offset's clamp passes gradient only where
+// The backward pass needs, of every row's v, only its minimum and second minimum
+// (values and edge indices) and the signs: the tape keeps that record per check
+// row and iteration (four words: m1, m2, the sign bits of v by edge, i1 | i2 << 8)
+// and E after every iteration. The backward pass walks layers and iterations in
+// reverse and propagates the adjoints of E and L. Ties go to the lowest edge
+// index, d|v|/dv is 0 at v = 0 and the offset's clamp passes gradient only where
 // min - beta > 0. Reductions run in a fixed order, so results are deterministic.
 //
 // Four lanes (a quad) share a row: lane q holds the row's edges
 // k in [q * S, (q + 1) * S), S = DMAX / 4, in registers. The row's sign parity,
 // minimum (with its edge index), second minimum (with its index) are combined
 // across the quad with two xor-shuffles; ties compare (value, index), so the
-// lowest index wins as in the sequential definition. L (and its adjoint) and the
-// tape's v are laid out per layer as [row][edge] (layer b starts at
-// blk_off[b] * Z), so a quad reads and writes contiguous words.
+// lowest index wins as in the sequential definition. L (and its adjoint) is laid
+// out per layer as [row][edge] (layer b starts at blk_off[b] * Z), so a quad
+// reads and writes contiguous words; lane q of a quad writes word q of the row's
+// tape record.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -192,12 +195,13 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
     for (size_t e = tid; e < ne; e += nthr)
         L[e] = 0.f;
     __syncthreads();
-    float *tape = A.tape + (size_t)f * T * (ne + n);
+    const size_t per_iter = (size_t)4 * C.m + ((n + 3) & ~3);  // row records, then E (16-byte rows)
+    float *tape = A.tape + (size_t)f * T * per_iter;
     const uint8_t *xb = A.xbits ? S.xb : nullptr;
     float loss = 0.f;
     for (int t = 0; t < T; ++t) {
         const float *bt = S.beta + t * C.n_blocks;
-        float *tv = tape + (size_t)t * (ne + n);
+        float *tv = tape + (size_t)t * per_iter;
         for (int b = 0; b < C.mb; ++b) {
             const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
             const size_t lb = (size_t)o * z;  // layer b's [row][edge] block
@@ -226,7 +230,6 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                         const int j = cs.x + rot(r, cs.y, z);
                         const size_t le = lb + (size_t)r * d + k;
                         const float vk = E[j] - L[le];
-                        tv[le] = vk;
                         v[s] = vk;
                         col[s] = j;
                         M.par ^= vk < 0.f;
@@ -244,6 +247,20 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                 }
                 M = quad_combine<1>(M);
                 M = quad_combine<2>(M);
+                // the row's tape record: sign bits of v by edge index, combined over the quad
+                unsigned sb = 0;
+#pragma unroll
+                for (int s = 0; s < SL; ++s)
+                    sb |= (unsigned)(v[s] < 0.f) << (q * SL + s);
+                sb |= (unsigned)quad_xor<1>((int)sb);
+                sb |= (unsigned)quad_xor<2>((int)sb);
+                if (act) {
+                    const float rec = q == 0   ? M.m1
+                                      : q == 1 ? M.m2
+                                      : q == 2 ? __builtin_bit_cast(float, sb)
+                                               : __builtin_bit_cast(float, M.i1 | M.i2 << 8);
+                    tv[(size_t)(b * z + r) * 4 + q] = rec;
+                }
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
@@ -259,7 +276,7 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
             __syncthreads();
         }
         // E after iteration t: to the tape, and into the loss
-        float *te = tv + ne;
+        float *te = tv + (size_t)4 * C.m;
         float part = 0.f;
         for (int j = tid; j < n; j += nthr) {
             const float e = E[j];
@@ -295,26 +312,23 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
     for (size_t e = tid; e < ne; e += nthr)
         Lb[e] = 0.f;
     __syncthreads();
-    const float *tape = A.tape + (size_t)f * T * (ne + n);
+    const size_t per_iter = (size_t)4 * C.m + ((n + 3) & ~3);  // row records, then E (16-byte rows)
+    const float *tape = A.tape + (size_t)f * T * per_iter;
     const uint8_t *xb = S.xb;
     const float g = A.dloss[f] / (float)n;
-    // The tape's v of the next row chunk in walk order (layers and iterations in
-    // reverse) is requested while the current chunk is processed, so its global
-    // latency overlaps that work and the layer barriers.
-    float vnext[SL];
-    auto fetch_v = [&](int t, int b, int r0) {
-        const int d = ldc(C.deg, b), r = r0 + rq;
-        const float *tvl = tape + (size_t)t * (ne + n) + (size_t)ldc(C.blk_off, b) * z;
-#pragma unroll
-        for (int s = 0; s < SL; ++s) {
-            const int k = q * SL + s;
-            vnext[s] = r < z && k < d ? tvl[(size_t)r * d + k] : 0.f;
-        }
+    // The tape record of the next row chunk in walk order (layers and iterations
+    // in reverse) is requested while the current chunk is processed, so its
+    // global latency overlaps that work and the layer barriers.
+    float4 rnext;
+    auto fetch_rec = [&](int t, int b, int r0) {
+        const int r = r0 + rq;
+        rnext = r < z ? reinterpret_cast<const float4 *>(tape + (size_t)t * per_iter)[(size_t)b * z + r]
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
     };
-    fetch_v(T - 1, C.mb - 1, 0);
+    fetch_rec(T - 1, C.mb - 1, 0);
     for (int t = T - 1; t >= 0; --t) {
         const float *bt = S.beta + t * C.n_blocks;
-        const float *tv = tape + (size_t)t * (ne + n);
+        const float *tv = tape + (size_t)t * per_iter;
         // the loss term of iteration t
         const float wt = (A.weights ? A.weights[t] : 1.f) * g;
         // four tape reads in flight per thread
@@ -323,7 +337,7 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + u * nthr;
-                e4[u] = j < n ? tv[ne + j] : 0.f;
+                e4[u] = j < n ? tv[(size_t)4 * C.m + j] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -345,24 +359,27 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
             for (int r0 = 0; r0 < z; r0 += nq) {
                 const int r = r0 + rq;
                 const bool act = r < z;
-                float v[SL], vb[SL];
+                float vb[SL];
                 int col[SL];
-#pragma unroll
-                for (int s = 0; s < SL; ++s)
-                    v[s] = vnext[s];
+                const float4 rec = rnext;
                 if (r0 + nq < z)
-                    fetch_v(t, b, r0 + nq);
+                    fetch_rec(t, b, r0 + nq);
                 else if (b > 0)
-                    fetch_v(t, b - 1, 0);
+                    fetch_rec(t, b - 1, 0);
                 else if (t > 0)
-                    fetch_v(t - 1, C.mb - 1, 0);
+                    fetch_rec(t - 1, C.mb - 1, 0);
+                // the forward pass's minima, indices and signs of this row
                 RowMin M;
-                M.m1 = M.m2 = INFINITY;
-                M.i1 = M.i2 = DMAX;
-                M.par = 0;
-                if (act && q == 0) {
+                M.m1 = rec.x;
+                M.m2 = rec.y;
+                const unsigned sb = __builtin_bit_cast(unsigned, rec.z);
+                const int ii = __builtin_bit_cast(int, rec.w);
+                M.i1 = ii & 0xff;
+                M.i2 = ii >> 8;
+                M.par = __builtin_popcount(sb) & 1;
+                if (act) {
                     const int i = b * z + r;
-                    M.par = (S.syn[i >> 3] >> (i & 7)) & 1;
+                    M.par ^= (S.syn[i >> 3] >> (i & 7)) & 1;
                 }
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
@@ -371,22 +388,8 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                     if (act && k < d) {
                         const int2 cs = S.blk[o + k];
                         col[s] = cs.x + rot(r, cs.y, z);
-                        const float vk = v[s];
-                        M.par ^= vk < 0.f;
-                        const float a = fabsf(vk);
-                        if (a < M.m1) {
-                            M.m2 = M.m1;
-                            M.i2 = M.i1;
-                            M.m1 = a;
-                            M.i1 = k;
-                        } else if (a < M.m2) {
-                            M.m2 = a;
-                            M.i2 = k;
-                        }
                     }
                 }
-                M = quad_combine<1>(M);
-                M = quad_combine<2>(M);
                 // adjoint of L_k (new) = its own adjoint + that of E_{j_k} (E = v + L)
                 float g_rest = 0.f, g_i1 = 0.f;
 #pragma unroll
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                         const int blk = o + k;
                         const float eb = Eb[col[s]];
                         const float a = Lb[lb + (size_t)r * d + k] + eb;
-                        const float sig = (M.par ^ (v[s] < 0.f)) ? -1.f : 1.f;
+                        const float sig = (M.par ^ ((sb >> k) & 1)) ? -1.f : 1.f;
                         const bool live = (k == M.i1 ? M.m2 : M.m1) - bt[blk] > 0.f;
                         const float gg = live ? a * sig : 0.f;
                         acc[s] -= gg;
@@ -417,11 +420,12 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
                     if (act && k < d) {
-                        const float sg = v[s] > 0.f ? 1.f : v[s] < 0.f ? -1.f : 0.f;
-                        if (k == M.i1)
-                            vb[s] += sg * g_rest;
-                        if (k == M.i2)
-                            vb[s] += sg * g_i1;
+                        // sgn(v_k): |v_i1| = m1, |v_i2| = m2, and the sign bit
+                        const float sgn = (sb >> k) & 1 ? -1.f : 1.f;
+                        if (k == M.i1 && M.m1 != 0.f)
+                            vb[s] += sgn * g_rest;
+                        if (k == M.i2 && M.m2 != 0.f)
+                            vb[s] += sgn * g_i1;
                         Eb[col[s]] = vb[s];
                         Lb[lb + (size_t)r * d + k] = -vb[s];
                     }

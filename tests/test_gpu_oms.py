@@ -163,6 +163,11 @@ def test_oms_argument_errors(B):
     assert lib.ldpc_oms_forward(code.handle, t.data_ptr(), t.data_ptr(), None, 1, 2, t.data_ptr(), None, None, None,
                                 t.data_ptr(), 16, None, 0, None) == B.LDPC_EINVAL          # short tape
     assert b"tape" in lib.ldpc_last_error()
+    # the tape's row records are read 16 bytes at a time: a misaligned tape is
+    # refused before anything is launched
+    assert lib.ldpc_oms_forward(code.handle, t.data_ptr(), t.data_ptr(), None, 1, 2, t.data_ptr(), None, None, None,
+                                t.data_ptr() + 4, 1 << 30, None, 0, None) == B.LDPC_EINVAL  # misaligned tape
+    assert b"aligned" in lib.ldpc_last_error()
     assert lib.ldpc_oms_forward(code.handle, t.data_ptr(), t.data_ptr(), None, 1, 2, None, None, None, None,
                                 t.data_ptr(), 1 << 30, None, 0, None) == B.LDPC_EINVAL     # beta NULL
     assert lib.ldpc_oms_backward(code.handle, t.data_ptr(), None, 1, 2, t.data_ptr(), None, t.data_ptr(),
