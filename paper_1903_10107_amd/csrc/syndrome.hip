@@ -67,6 +67,61 @@ __global__ __launch_bounds__(1024) void k_syndrome_lds(DevCode C, const uint8_t 
     }
 }
 
+// Word-parallel form for Z a multiple of 32. Block b of s is the XOR over its
+// nonzero base entries of the column block x_c cyclically rotated by the shift:
+// s[bZ + r] ^= x[cZ + (r + s) mod Z]. With Z = 32 W, output word k of a block
+// takes bits 32 k + s .. 32 k + s + 31 (mod Z) of x_c, i.e. words (k + s/32) and
+// (k + s/32 + 1) mod W funnel-shifted right by s mod 32: one alignbit and one XOR
+// per block and 32 syndrome bits, instead of 32 single-bit gathers.
+//
+// The code's tables are staged in LDS first, per workgroup: for every nonzero
+// block, int2{word index of its column block in x, (s mod 32) | (s / 32) << 5},
+// and for every base row int2{first block, degree}.
+__device__ __forceinline__ void stage_syndrome_tables(const DevCode &C, int2 *tab, int2 *rows, int tid, int nthr)
+{
+    for (int e = tid; e < C.n_blocks; e += nthr) {
+        const int sh = C.shift[e];
+        tab[e] = make_int2(C.colbase[e] >> 5, (sh & 31) | (sh >> 5) << 5);
+    }
+    for (int b = tid; b < C.mb; b += nthr)
+        rows[b] = make_int2(C.blk_off[b], C.deg[b]);
+}
+
+// Syndrome word w of one frame.
+__device__ __forceinline__ uint32_t syndrome_word(const int2 *tab, const int2 *rows, int wz, const uint32_t *x, int w)
+{
+    const int b = w / wz, k = w - b * wz;
+    const int2 r = rows[b];
+    uint32_t acc = 0;
+#pragma unroll 4
+    for (int e = r.x; e < r.x + r.y; ++e) {
+        const int2 t = tab[e];
+        int u = k + (t.y >> 5);
+        u = u >= wz ? u - wz : u;
+        const int u1 = u + 1 == wz ? 0 : u + 1;
+        acc ^= __builtin_amdgcn_alignbit(x[t.x + u1], x[t.x + u], (uint32_t)(t.y & 31));
+    }
+    return acc;
+}
+
+// One thread per (frame, syndrome word), grid-stride; x is read through the
+// caches (each word of x serves about six alignbits), the code's tables from LDS.
+__global__ __launch_bounds__(256) void k_syndrome_words(DevCode C, const uint32_t *__restrict__ bits, int n_frames,
+                                                        uint32_t *__restrict__ out_syn)
+{
+    extern __shared__ __align__(16) int2 s_tab[];
+    int2 *s_rows = s_tab + C.n_blocks;
+    const int wz = C.z >> 5, xw = C.n >> 5, sw = C.m >> 5;
+    stage_syndrome_tables(C, s_tab, s_rows, threadIdx.x, blockDim.x);
+    __syncthreads();
+    const long long total = (long long)n_frames * sw;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x) {
+        const int f = (int)(g / sw), w = (int)(g - (long long)f * sw);
+        out_syn[g] = syndrome_word(s_tab, s_rows, wz, bits + (size_t)f * xw, w);
+    }
+}
+
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s)
 {
     const int bit_bytes = (C.n + 7) / 8, syn_bytes = (C.m + 7) / 8;
@@ -76,6 +131,26 @@ hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, 
         e0 = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e0 != hipSuccess)
         return e0;
+    // Z a multiple of 32 makes every block, frame row and syndrome row whole
+    // 32-bit words; the word kernels also need 4-byte aligned buffers
+    if (C.z % 32 == 0 && ((uintptr_t)bits | (uintptr_t)out_syn) % 4 == 0) {
+        const uint32_t *xw = reinterpret_cast<const uint32_t *>(bits);
+        uint32_t *sw = reinterpret_cast<uint32_t *>(out_syn);
+        const int words = C.m >> 5;
+        const size_t tab_bytes = ((size_t)C.n_blocks + C.mb) * sizeof(int2);
+        if (tab_bytes <= (size_t)lds_limit) {
+            if (tab_bytes > 65536) {
+                hipError_t e = allow_max_lds<k_syndrome_words>();
+                if (e != hipSuccess)
+                    return e;
+            }
+            const long long total = (long long)n_frames * words;
+            const long long blocks = (total + 255) / 256;
+            hipLaunchKernelGGL(k_syndrome_words, dim3((unsigned)(blocks < (1 << 20) ? blocks : (1 << 20))),
+                               dim3(256), tab_bytes, s, C, xw, n_frames, sw);
+            return hipGetLastError();
+        }
+    }
     // one workgroup per frame fills the chip only with many frames; a few long
     // frames go row-parallel instead
     if (bit_bytes <= lds_limit && n_frames >= 128) {

@@ -183,19 +183,35 @@ def test_binding_rejects_short_buffers(B):
         B.ldpc_decode_batch(code, syn, llr, 4, 10, bits, conv)
 
 
-def test_syndrome_encoder_matches_generator(B):
+@pytest.mark.parametrize("mb,nb,z,frames,misalign", [
+    (5, 32, 32, 5, 0),       # word kernel (Z a multiple of 32), one partial workgroup
+    (4, 12, 37, 5, 0),       # Z not a multiple of 32: bit kernel
+    (5, 32, 1024, 5, 0),     # word kernel, the n = 32768 code
+    (5, 32, 1024, 300, 0),   # word kernel, many frames (workgroups span frames)
+    (3, 8, 96, 130, 0),      # Z = 3 x 32, not a power of two: 3 words per block
+    (5, 32, 1024, 130, 1),   # buffers not 4-byte aligned: bit kernel with the frame in LDS
+    (5, 32, 1024, 5, 1),     # the same with few frames: row-parallel bit kernel
+    (3, 7, 45, 200, 0),      # odd Z with many frames: bit kernel with LDS
+])
+def test_syndrome_encoder_matches_generator(B, mb, nb, z, frames, misalign):
     import torch
-    for (mb, nb, z) in ((5, 32, 32), (4, 12, 37), (5, 32, 1024)):
-        base = I.make_base(mb, nb, z, 3, 11)
-        code = I.Code(base, z)
-        fr = I.make_frames(code, 5, 0.05, 12)
-        gc = B.Code(base, z)
-        _say(f"[gpu syndrome] n={code.n}")
-        xb = torch.from_numpy(I.pack_bits(fr.x)).cuda()
-        out = torch.zeros((5, (code.m + 7) // 8), dtype=torch.uint8, device="cuda")
-        B.ldpc_syndrome_batch(gc, xb, 5, out)
-        torch.cuda.synchronize()
-        assert np.array_equal(out.cpu().numpy(), fr.syn)
+    base = I.make_base(mb, nb, z, 3, 11)
+    code = I.Code(base, z)
+    rng = np.random.default_rng(12 + frames)
+    x = rng.integers(0, 2, size=(frames, code.n), dtype=np.uint8)
+    ref = I.pack_bits(I.syndrome_bits(code, x))
+    gc = B.Code(base, z)
+    _say(f"[gpu syndrome] n={code.n} frames={frames} misalign={misalign}")
+    bb, sb = (code.n + 7) // 8, (code.m + 7) // 8
+    xflat = torch.zeros(misalign + frames * bb, dtype=torch.uint8, device="cuda")
+    xb = xflat[misalign:].view(frames, bb)
+    xb.copy_(torch.from_numpy(I.pack_bits(x)))
+    oflat = torch.zeros(misalign + frames * sb, dtype=torch.uint8, device="cuda")
+    out = oflat[misalign:].view(frames, sb)
+    B.ldpc_syndrome_batch(gc, xb, frames, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert int(oflat[:misalign].sum()) == 0
 
 
 def _full_size(B, wl_name, sample, seed=10107):
