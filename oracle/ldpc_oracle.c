@@ -322,9 +322,10 @@ int oracle_decode(const int32_t *base, int mb, int nb, int z, const oracle_param
     const size_t sb = (size_t)(g.m + 7) / 8, nbits = (size_t)(g.n + 7) / 8;
     const size_t ne = (size_t)g.n_blocks * (size_t)z;
 #ifdef _OPENMP
-    if (n_threads > 0)
-        omp_set_num_threads(n_threads);
-#pragma omp parallel for schedule(dynamic, 1)
+    /* a thread count for this call only (a num_threads clause, not the
+     * process-wide default, so a one-thread call leaves later calls alone) */
+    const int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
 #endif
     for (int f = 0; f < n_frames; f++) {
         int it = decode_frame(&g, prm, syn + (size_t)f * sb, llr + (size_t)f * (size_t)g.n, max_iter,
@@ -424,9 +425,10 @@ int oracle_bp_fp64_decode(const int32_t *base, int mb, int nb, int z,
         }
     const size_t sb = (size_t)(g.m + 7) / 8, nbits = (size_t)(g.n + 7) / 8;
 #ifdef _OPENMP
-    if (n_threads > 0)
-        omp_set_num_threads(n_threads);
-#pragma omp parallel for schedule(dynamic, 1)
+    /* a thread count for this call only (a num_threads clause, not the
+     * process-wide default, so a one-thread call leaves later calls alone) */
+    const int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
 #endif
     for (int f = 0; f < n_frames; f++) {
         const int n = g.n, m = g.m;

@@ -157,6 +157,22 @@ def test_converged_frames_satisfy_the_syndrome_and_mostly_recover_x():
     assert (r["iters"][~ok] == 50).all()
 
 
+def test_thread_count_is_per_call():
+    """A decode on one thread gives the same result as on all threads and leaves
+    the thread count of later calls as it was."""
+    code = _code()
+    fr = I.make_frames(code, 12, 0.01, 6)
+    before = O.max_threads()
+    one = O.decode(code.base, code.z, fr.syn, fr.llr, 50, n_threads=1)
+    assert O.max_threads() == before
+    r = O.bp_fp64_decode(code.base, code.z, fr.syn, fr.llr.astype(np.float64), 10, n_threads=1)
+    assert O.max_threads() == before
+    full = O.decode(code.base, code.z, fr.syn, fr.llr, 50)
+    for k in ("bits", "conv", "iters"):
+        assert np.array_equal(one[k], full[k])
+    assert r["conv"].shape == (12,)
+
+
 def test_acc16_soft_value_is_llr_plus_incoming_messages():
     code = _code()
     fr = I.make_frames(code, 12, 0.03, 6)
