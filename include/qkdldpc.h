@@ -274,9 +274,11 @@ int ldpc_reveal_batch(const ldpc_code *code, int8_t *llr, int32_t n_frames, cons
  *                 written by the forward pass, read by the backward pass (per
  *                 check row and iteration the two smallest |VN->CN| values, their
  *                 edge indices and the signs; soft values after every iteration)
- *   workspace     ldpc_oms_workspace_bytes(code, F, n_iter) bytes (may be NULL
- *                 when that is 0 for the forward pass): FP32 state of codes whose
- *                 state does not fit in LDS, and per-frame offset gradients
+ *   workspace     ldpc_oms_workspace_bytes(code, F, n_iter) bytes: FP32 state of
+ *                 codes whose state does not fit in LDS, and per-frame offset
+ *                 gradients. The forward pass keeps E and one record per check
+ *                 row (not a value per edge), so it reads the workspace only when
+ *                 that smaller state does not fit in LDS; otherwise it may be NULL.
  * Returns LDPC_EINVAL for bad arguments (n_iter < 1, NULL pointers, short or
  * misaligned tape, short workspace), LDPC_EUNSUPPORTED when the offset table (n_iter x n_blocks
  * floats) does not fit in on-chip memory, LDPC_EDEVICE for launch failures.

@@ -397,10 +397,16 @@ qkdldpc::OmsPlan oms_plan(const ldpc_code *c, int32_t n_iter, bool *fits = nullp
     const size_t fixed = (size_t)16 * P.dmax * sizeof(float) + (size_t)std::max(n_iter, 0) * h.n_blocks * sizeof(float) +
                          (size_t)h.n_blocks * 8 + 16 + round_up((size_t)(h.m + 7) / 8, 16) +
                          round_up((size_t)(h.n + 7) / 8, 16);
-    const size_t st = ((size_t)h.n + ne) * sizeof(float);
+    // state: backward the adjoints of E and L, forward E and a four-word record
+    // per check row; each array padded to a multiple of four floats
+    const size_t n4 = round_up((size_t)h.n, 4);
+    const size_t st = (n4 + round_up(ne, 4)) * sizeof(float);
+    const size_t st_f = (n4 + (size_t)4 * h.m) * sizeof(float);
     const size_t limit = (size_t)(c->lds_limit - 1024);
     P.lds_state = st + fixed <= limit;
     P.lds_bytes = (P.lds_state ? st : 0) + fixed;
+    P.fwd_lds_state = st_f + fixed <= limit;
+    P.fwd_lds_bytes = (P.fwd_lds_state ? st_f : 0) + fixed;
     if (fits)
         *fits = fixed <= limit;
     return P;
@@ -412,11 +418,15 @@ size_t oms_tape_floats(const HostCode &h, int32_t n_iter)
     return (size_t)n_iter * ((size_t)4 * h.m + (((size_t)h.n + 3) & ~(size_t)3));
 }
 
+// Global slices (per frame) for whichever pass's state does not fit in LDS; the
+// two passes never run at once, so they share the slices.
 size_t oms_state_bytes(const ldpc_code *c, const qkdldpc::OmsPlan &P, int32_t n_frames)
 {
-    if (P.lds_state)
-        return 0;
-    return round_up(((size_t)c->h.n + (size_t)c->h.n_blocks * c->h.z) * sizeof(float) * n_frames, 256);
+    const size_t n4 = round_up((size_t)c->h.n, 4);
+    const size_t bwd = P.lds_state ? 0 : n4 + round_up((size_t)c->h.n_blocks * c->h.z, 4);
+    const size_t fwd = P.fwd_lds_state ? 0 : n4 + (size_t)4 * c->h.m;
+    const size_t per = std::max(bwd, fwd);
+    return per ? round_up(per * sizeof(float) * n_frames, 256) : 0;
 }
 
 int oms_check(const ldpc_code *code, const char *who, const uint8_t *syndromes, int32_t n_frames, int32_t n_iter,
@@ -458,7 +468,7 @@ qkdldpc::OmsArgs oms_args(const ldpc_code *code, const uint8_t *syndromes, const
     A.syn_bytes = (code->h.m + 7) / 8;
     A.bit_bytes = (code->h.n + 7) / 8;
     A.tape = static_cast<float *>(tape);
-    A.state = P.lds_state ? nullptr : static_cast<float *>(workspace);
+    A.state = P.lds_state && P.fwd_lds_state ? nullptr : static_cast<float *>(workspace);
     return A;
 }
 
@@ -865,7 +875,8 @@ int ldpc_oms_forward(const ldpc_code *code, const uint8_t *syndromes, const floa
     if (out_loss && !target_bits)
         return fail(LDPC_EINVAL, "ldpc_oms_forward: out_loss needs target_bits");
     const qkdldpc::OmsPlan P = oms_plan(code, n_iter);
-    const size_t need = oms_state_bytes(code, P, n_frames);
+    // the forward reads the workspace only when its own state does not fit in LDS
+    const size_t need = P.fwd_lds_state ? 0 : oms_state_bytes(code, P, n_frames);
     if (need && (!workspace || workspace_bytes < need))
         return fail(LDPC_EINVAL, "ldpc_oms_forward: workspace smaller than ldpc_oms_workspace_bytes");
     qkdldpc::OmsArgs A = oms_args(code, syndromes, target_bits, n_frames, n_iter, beta, loss_weights, tape,

@@ -13,7 +13,10 @@
 // The backward pass needs, of every row's v, only its minimum and second minimum
 // (values and edge indices) and the signs: the tape keeps that record per check
 // row and iteration (four words: m1, m2, the sign bits of v by edge, i1 | i2 << 8)
-// and E after every iteration. The backward pass walks layers and iterations in
+// and E after every iteration. The same record and the offsets of its iteration
+// give every L_k of the row, so the forward pass keeps E and one record per row
+// on chip instead of a value per edge (for n = 8192 that is 53 KB instead of
+// 128 KB, and two frames share a CU). The backward pass walks layers and iterations in
 // reverse and propagates the adjoints of E and L. Ties go to the lowest edge
 // index, d|v|/dv is 0 at v = 0 and the offset's clamp passes gradient only where
 // min - beta > 0. Reductions run in a fixed order, so results are deterministic.
@@ -22,10 +25,10 @@
 // k in [q * S, (q + 1) * S), S = DMAX / 4, in registers. The row's sign parity,
 // minimum (with its edge index), second minimum (with its index) are combined
 // across the quad with two xor-shuffles; ties compare (value, index), so the
-// lowest index wins as in the sequential definition. L (and its adjoint) is laid
+// lowest index wins as in the sequential definition. The adjoint of L is laid
 // out per layer as [row][edge] (layer b starts at blk_off[b] * Z), so a quad
 // reads and writes contiguous words; lane q of a quad writes word q of the row's
-// tape record.
+// record.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -123,7 +126,8 @@ __device__ __forceinline__ RowMin quad_combine(RowMin a)
 }
 
 struct OmsState {
-    float *E, *L;      // E [n], L [n_blocks * Z] (forward) or their adjoints (backward)
+    float *E, *L;      // forward: E [n] and the row records [m][4] (at a 16-byte
+                       // boundary); backward: the adjoints of E [n] and L [n_blocks * Z]
     int2 *blk;         // per block {column start c*Z, circulant shift}, staged in LDS
     float *beta;       // offsets [T][n_blocks] staged in LDS
     float *red;        // reduction scratch
@@ -133,19 +137,23 @@ struct OmsState {
 
 // LDS: [state if LDS] [block table, 16-byte aligned] [beta T * n_blocks] [red] [syndrome,
 // 16-byte padded] [target bits]
-__device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A, bool lds, int red_floats)
+// second: floats of the second state array (4m forward, n_blocks * Z backward).
+// Both arrays start at 16-byte boundaries (each is padded to a multiple of four
+// floats), in LDS and in the per-frame global slices alike.
+__device__ __forceinline__ OmsState oms_state(const DevCode &C, const OmsArgs &A, bool lds, int red_floats,
+                                              size_t second)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     OmsState S;
-    const size_t ne = (size_t)C.n_blocks * C.z;
+    const size_t n4 = ((size_t)C.n + 3) & ~(size_t)3, st = n4 + ((second + 3) & ~(size_t)3);
     uint8_t *p = smem;
     if (lds) {
         S.E = reinterpret_cast<float *>(p);
-        S.L = S.E + C.n;
-        p += ((C.n + ne) * sizeof(float) + 15) & ~(size_t)15;
+        S.L = S.E + n4;
+        p += st * sizeof(float);
     } else {
-        S.E = A.state + (size_t)blockIdx.x * (C.n + ne);
-        S.L = S.E + C.n;
+        S.E = A.state + (size_t)blockIdx.x * st;
+        S.L = S.E + n4;
     }
     S.blk = reinterpret_cast<int2 *>(p);
     p += (size_t)C.n_blocks * sizeof(int2);
@@ -178,22 +186,26 @@ __device__ __forceinline__ void stage_common(const DevCode &C, const OmsArgs &A,
 
 } // namespace
 
+// Two workgroups per CU for rows of up to 20 edges with the state in LDS (64
+// VGPRs, and the forward state E + row records is small enough for two in LDS).
 template <int DMAX, bool LDS>
-__global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(DMAX <= 20 && LDS ? 8 : 1)))
+void k_oms_forward(DevCode C, OmsArgs A)
 {
     constexpr int SL = DMAX / kQuad;  // edges per lane
     const int f = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
     const int z = C.z, n = C.n, T = A.n_iter;
     const int q = tid & (kQuad - 1), rq = tid / kQuad, nq = nthr / kQuad;
-    const size_t ne = (size_t)C.n_blocks * z;
-    OmsState S = oms_state(C, A, LDS, 16);
-    float *E = S.E, *L = S.L;
+    OmsState S = oms_state(C, A, LDS, 16, (size_t)4 * C.m);
+    float *E = S.E;
+    // The row's CN->VN values of the last iteration are a function of its record
+    // (m1, m2, sign bits, i1 | i2 << 8) and that iteration's offsets, so the
+    // forward keeps one record per row instead of a value per edge.
+    float4 *Rec = reinterpret_cast<float4 *>(S.L);
     stage_common(C, A, S);
     const float *llr = A.llr + (size_t)f * n;
     for (int j = tid; j < n; j += nthr)
         E[j] = llr[j];
-    for (size_t e = tid; e < ne; e += nthr)
-        L[e] = 0.f;
     __syncthreads();
     const size_t per_iter = (size_t)4 * C.m + ((n + 3) & ~3);  // row records, then E (16-byte rows)
     float *tape = A.tape + (size_t)f * T * per_iter;
@@ -201,25 +213,30 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
     float loss = 0.f;
     for (int t = 0; t < T; ++t) {
         const float *bt = S.beta + t * C.n_blocks;
+        const float *bp = S.beta + (t > 0 ? t - 1 : 0) * C.n_blocks;  // offsets of the record's iteration
         float *tv = tape + (size_t)t * per_iter;
         for (int b = 0; b < C.mb; ++b) {
             const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
-            const size_t lb = (size_t)o * z;  // layer b's [row][edge] block
             // all lanes of a quad take part in the shuffles, so the row loop is
             // uniform across the quad (rows past Z are masked per lane)
             for (int r0 = 0; r0 < z; r0 += nq) {
                 const int r = r0 + rq;
                 const bool act = r < z;
+                const int i = b * z + r;
+                const int sbit = act ? (S.syn[i >> 3] >> (i & 7)) & 1 : 0;
+                // the row's record of iteration t - 1 (all four lanes read the same 16 bytes)
+                float4 rp = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (act && t > 0)
+                    rp = Rec[i];
+                const unsigned psb = __builtin_bit_cast(unsigned, rp.z);
+                const int pi1 = __builtin_bit_cast(int, rp.w) & 0xff;
+                const unsigned ppar = (unsigned)sbit ^ (__builtin_popcount(psb) & 1);
                 float v[SL];
                 int col[SL];
                 RowMin M;
                 M.m1 = M.m2 = INFINITY;
                 M.i1 = M.i2 = DMAX;
-                M.par = 0;
-                if (act && q == 0) {
-                    const int i = b * z + r;
-                    M.par = (S.syn[i >> 3] >> (i & 7)) & 1;
-                }
+                M.par = q == 0 ? sbit : 0;
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
@@ -228,8 +245,13 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                     if (act && k < d) {
                         const int2 cs = S.blk[o + k];
                         const int j = cs.x + rot(r, cs.y, z);
-                        const size_t le = lb + (size_t)r * d + k;
-                        const float vk = E[j] - L[le];
+                        // L of this edge from iteration t - 1 (0 before the first)
+                        float lo = 0.f;
+                        if (t > 0) {
+                            const float mag = fmaxf((k == pi1 ? rp.y : rp.x) - bp[o + k], 0.f);
+                            lo = (ppar ^ ((psb >> k) & 1)) ? -mag : mag;
+                        }
+                        const float vk = E[j] - lo;
                         v[s] = vk;
                         col[s] = j;
                         M.par ^= vk < 0.f;
@@ -247,7 +269,8 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                 }
                 M = quad_combine<1>(M);
                 M = quad_combine<2>(M);
-                // the row's tape record: sign bits of v by edge index, combined over the quad
+                // the row's record: sign bits of v by edge index, combined over the quad;
+                // lane q writes word q, to LDS (read back in iteration t + 1) and to the tape
                 unsigned sb = 0;
 #pragma unroll
                 for (int s = 0; s < SL; ++s)
@@ -259,16 +282,15 @@ __global__ __launch_bounds__(1024) void k_oms_forward(DevCode C, OmsArgs A)
                                       : q == 1 ? M.m2
                                       : q == 2 ? __builtin_bit_cast(float, sb)
                                                : __builtin_bit_cast(float, M.i1 | M.i2 << 8);
-                    tv[(size_t)(b * z + r) * 4 + q] = rec;
+                    S.L[(size_t)i * 4 + q] = rec;
+                    tv[(size_t)i * 4 + q] = rec;
                 }
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
                     const int k = q * SL + s;
                     if (act && k < d) {
-                        const int blk = o + k;
-                        const float mag = fmaxf((k == M.i1 ? M.m2 : M.m1) - bt[blk], 0.f);
+                        const float mag = fmaxf((k == M.i1 ? M.m2 : M.m1) - bt[o + k], 0.f);
                         const float ln = (M.par ^ (v[s] < 0.f)) ? -mag : mag;
-                        L[lb + (size_t)r * d + k] = ln;
                         E[col[s]] = v[s] + ln;
                     }
                 }
@@ -304,7 +326,7 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
     const int q = tid & (kQuad - 1), rq = tid / kQuad, nq = nthr / kQuad;
     const int lane = tid & 63, w = tid >> 6, nw = nthr >> 6;
     const size_t ne = (size_t)C.n_blocks * z;
-    OmsState S = oms_state(C, A, LDS, 16 * DMAX);
+    OmsState S = oms_state(C, A, LDS, 16 * DMAX, ne);
     float *Eb = S.E, *Lb = S.L;  // adjoints of E and L
     stage_common(C, A, S);
     for (int j = tid; j < n; j += nthr)
@@ -500,20 +522,22 @@ namespace {
 template <int DMAX>
 hipError_t fwd(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t s)
 {
-    if (P.lds_state) {
-        if (P.lds_bytes > 65536) {
+    if (P.fwd_lds_state) {
+        if (P.fwd_lds_bytes > 65536) {
             hipError_t e = allow_max_lds<k_oms_forward<DMAX, true>>();
             if (e != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL((k_oms_forward<DMAX, true>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
+        hipLaunchKernelGGL((k_oms_forward<DMAX, true>), dim3(A.n_frames), dim3(P.threads), P.fwd_lds_bytes, s, C,
+                           A);
     } else {
-        if (P.lds_bytes > 65536) {
+        if (P.fwd_lds_bytes > 65536) {
             hipError_t e = allow_max_lds<k_oms_forward<DMAX, false>>();
             if (e != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL((k_oms_forward<DMAX, false>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
+        hipLaunchKernelGGL((k_oms_forward<DMAX, false>), dim3(A.n_frames), dim3(P.threads), P.fwd_lds_bytes, s, C,
+                           A);
     }
     return hipGetLastError();
 }

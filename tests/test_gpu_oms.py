@@ -66,11 +66,13 @@ def _case(mb, nb, z, cw, F, q, T, seed, dyadic=True):
     return code, fr, llr, beta, weights, dloss
 
 
-@pytest.mark.parametrize("shape", [(5, 32, 32, 3), (5, 32, 1024, 3), (8, 16, 64, 2), (2, 24, 64, 2)],
-                         ids=["n1024_dmax20_lds", "n32768_global_state", "n1024_dmax8", "n1536_deg24_dmax32"])
+@pytest.mark.parametrize("shape", [(5, 32, 32, 3), (5, 32, 1024, 3), (5, 32, 512, 3), (8, 16, 64, 2),
+                                   (2, 24, 64, 2)],
+                         ids=["n1024_dmax20_lds", "n32768_global_state", "n16384_fwd_lds_bwd_global", "n1024_dmax8",
+                              "n1536_deg24_dmax32"])
 def test_forward_and_gradients_match_fp64(B, shape):
     mb, nb, z, cw = shape
-    F, T = (2, 3) if z >= 1024 else (6, 5)
+    F, T = (2, 3) if z >= 512 else (6, 5)
     code, fr, llr, beta, weights, dloss = _case(mb, nb, z, cw, F, 0.04, T, 11 + z)
     _say(f"[gpu oms] n={code.n} F={F} T={T}")
     loss, E, db, dl = _gpu_loss_grad(B, code.base, z, fr, llr, beta, weights, dloss, T)
