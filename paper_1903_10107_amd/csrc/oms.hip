@@ -317,7 +317,13 @@ void k_oms_forward(DevCode C, OmsArgs A)
             A.out_E[(size_t)f * n + j] = E[j];
 }
 
-template <int DMAX, bool LDS>
+// MBR > 0: the adjoint of L lives in registers, MBR layers of SL slots per lane.
+// That needs every row of a layer handled by one quad in one pass (4 Z <= the
+// workgroup) and at most MBR layers; each lane then owns the same row and edge
+// slots in every layer and iteration, so the adjoint it reads is the one it
+// wrote. Otherwise (MBR = 0) the adjoint of L is laid out [layer][row][edge] in
+// the state.
+template <int DMAX, bool LDS, int MBR>
 __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
 {
     constexpr int SL = DMAX / kQuad;
@@ -331,8 +337,15 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
     stage_common(C, A, S);
     for (int j = tid; j < n; j += nthr)
         Eb[j] = 0.f;
-    for (size_t e = tid; e < ne; e += nthr)
-        Lb[e] = 0.f;
+    if constexpr (MBR == 0)
+        for (size_t e = tid; e < ne; e += nthr)
+            Lb[e] = 0.f;
+    float lreg[MBR > 0 ? MBR : 1][SL];
+#pragma unroll
+    for (int b = 0; b < (MBR > 0 ? MBR : 1); ++b)
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+            lreg[b][s] = 0.f;
     __syncthreads();
     const size_t per_iter = (size_t)4 * C.m + ((n + 3) & ~3);  // row records, then E (16-byte rows)
     const float *tape = A.tape + (size_t)f * T * per_iter;
@@ -371,7 +384,8 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
             }
         }
         __syncthreads();
-        for (int b = C.mb - 1; b >= 0; --b) {
+        // layer b; lr: this lane's register adjoints of L for the layer (MBR > 0)
+        auto layer = [&](int b, float(&lr)[SL]) {
             const int d = ldc(C.deg, b), o = ldc(C.blk_off, b);
             const size_t lb = (size_t)o * z;
             float acc[SL];
@@ -421,7 +435,7 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                     if (act && k < d) {
                         const int blk = o + k;
                         const float eb = Eb[col[s]];
-                        const float a = Lb[lb + (size_t)r * d + k] + eb;
+                        const float a = (MBR > 0 ? lr[s] : Lb[lb + (size_t)r * d + k]) + eb;
                         const float sig = (M.par ^ ((sb >> k) & 1)) ? -1.f : 1.f;
                         const bool live = (k == M.i1 ? M.m2 : M.m1) - bt[blk] > 0.f;
                         const float gg = live ? a * sig : 0.f;
@@ -449,7 +463,10 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                         if (k == M.i2 && M.m2 != 0.f)
                             vb[s] += sgn * g_i1;
                         Eb[col[s]] = vb[s];
-                        Lb[lb + (size_t)r * d + k] = -vb[s];
+                        if constexpr (MBR > 0)
+                            lr[s] = -vb[s];
+                        else
+                            Lb[lb + (size_t)r * d + k] = -vb[s];
                     }
                 }
             }
@@ -472,6 +489,15 @@ __global__ __launch_bounds__(1024) void k_oms_backward(DevCode C, OmsArgs A)
                 A.dbeta_frames[((size_t)f * T + t) * C.n_blocks + o + tid] = s;
             }
             __syncthreads();
+        };
+        if constexpr (MBR > 0) {
+#pragma unroll
+            for (int b = MBR - 1; b >= 0; --b)
+                if (b < C.mb)
+                    layer(b, lreg[b]);
+        } else {
+            for (int b = C.mb - 1; b >= 0; --b)
+                layer(b, lreg[0]);
         }
     }
     if (A.dllr)
@@ -542,26 +568,38 @@ hipError_t fwd(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t
     return hipGetLastError();
 }
 
+template <int DMAX, bool LDS, int MBR>
+hipError_t bwd_launch(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t s)
+{
+    if (P.lds_bytes > 65536) {
+        hipError_t e = allow_max_lds<k_oms_backward<DMAX, LDS, MBR>>();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL((k_oms_backward<DMAX, LDS, MBR>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
+    return hipGetLastError();
+}
+
+// layers whose adjoint of L the backward keeps in registers (row degrees up to 20)
+constexpr int kBwdRegLayers = 8;
+
 template <int DMAX>
 hipError_t bwd(const OmsPlan &P, const DevCode &C, const OmsArgs &A, hipStream_t s)
 {
+    // one pass of the quads covers a layer's rows, and few enough layers
+    const bool regs = DMAX <= 20 && P.threads / kQuad >= C.z && C.mb <= kBwdRegLayers;
+    hipError_t e0 = hipSuccess;
     if (A.n_frames == 0) {
         // nothing to differentiate: the frame sum writes zeros
     } else if (P.lds_state) {
-        if (P.lds_bytes > 65536) {
-            hipError_t e = allow_max_lds<k_oms_backward<DMAX, true>>();
-            if (e != hipSuccess)
-                return e;
-        }
-        hipLaunchKernelGGL((k_oms_backward<DMAX, true>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
+        e0 = regs ? bwd_launch<DMAX, true, DMAX <= 20 ? kBwdRegLayers : 0>(P, C, A, s)
+                  : bwd_launch<DMAX, true, 0>(P, C, A, s);
     } else {
-        if (P.lds_bytes > 65536) {
-            hipError_t e = allow_max_lds<k_oms_backward<DMAX, false>>();
-            if (e != hipSuccess)
-                return e;
-        }
-        hipLaunchKernelGGL((k_oms_backward<DMAX, false>), dim3(A.n_frames), dim3(P.threads), P.lds_bytes, s, C, A);
+        e0 = regs ? bwd_launch<DMAX, false, DMAX <= 20 ? kBwdRegLayers : 0>(P, C, A, s)
+                  : bwd_launch<DMAX, false, 0>(P, C, A, s);
     }
+    if (e0 != hipSuccess)
+        return e0;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
