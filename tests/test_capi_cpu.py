@@ -147,3 +147,13 @@ def test_one_hip_runtime_in_the_process():
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_c_client_links_and_loads_without_a_gpu():
+    """The plain C client of the ABI is built, and its loader finds libqkdldpc and
+    the HIP runtime (run without arguments it prints its usage before any HIP call)."""
+    import subprocess
+    client = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_client", "decode_client")
+    assert os.path.exists(client), "build() builds tests/c_client/decode_client"
+    out = subprocess.run([client], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 1 and "usage" in out.stderr, out.stderr
