@@ -67,9 +67,9 @@ def _case(mb, nb, z, cw, F, q, T, seed, dyadic=True):
 
 
 @pytest.mark.parametrize("shape", [(5, 32, 32, 3), (5, 32, 1024, 3), (5, 32, 512, 3), (8, 16, 64, 2),
-                                   (2, 24, 64, 2)],
+                                   (2, 24, 64, 2), (3, 7, 45, 2)],
                          ids=["n1024_dmax20_lds", "n32768_global_state", "n16384_fwd_lds_bwd_global", "n1024_dmax8",
-                              "n1536_deg24_dmax32"])
+                              "n1536_deg24_dmax32", "n315_odd_n_dmax8"])
 def test_forward_and_gradients_match_fp64(B, shape):
     mb, nb, z, cw = shape
     F, T = (2, 3) if z >= 512 else (6, 5)
