@@ -205,7 +205,9 @@ def fer_sweep(wl, code, fracs, n_frames: int, qbers=None):
 def batched(wl, code, n_short, n_frames, steps, warmup):
     """The same workload with many batches decoded per launch, under the fastest
     of a few frame schedules (one workgroup per frame, or persistent workgroups
-    pulling frames from a queue); the schedule is picked by the autotuner."""
+    pulling frames from a queue, as given or with the frames whose hard decision
+    fails the most checks first, that order computed on the GPU inside every
+    timed step); the schedule is picked by the autotuner."""
     import numpy as np
     import torch
     from paper_1903_10107_amd import inputs as I
@@ -215,7 +217,8 @@ def batched(wl, code, n_short, n_frames, steps, warmup):
     fr = I.make_frames(code, n_frames, wl.qber, 10107, n_short=n_short)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     cands = [tune.Schedule("auto", 0, "none", False), tune.Schedule("split", n_cu, "none", False),
-             tune.Schedule("split", 2 * n_cu, "none", False), tune.Schedule("split", 2 * n_cu, "none", True)]
+             tune.Schedule("split", 2 * n_cu, "none", False), tune.Schedule("split", 2 * n_cu, "none", True),
+             tune.Schedule("split", n_cu, "unsat_first", True), tune.Schedule("split", 2 * n_cu, "unsat_first", True)]
     best = tune.tune(code.base, code.z, fr.syn, fr.llr, wl.max_iter, acc_bits=wl.acc_bits, cache_path=None,
                      cands=cands, reps=2)
     sched = tune.Schedule(**best["schedule"])
@@ -252,7 +255,8 @@ def ragged(n_frames, steps, warmup):
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     cands = [tune.Schedule("auto", 0, "none", False), tune.Schedule("auto", n_cu, "none", False),
              tune.Schedule("auto", 2 * n_cu, "none", False), tune.Schedule("auto", 2 * n_cu, "hardest_first", False),
-             tune.Schedule("auto", 2 * n_cu, "hardest_first", True)]
+             tune.Schedule("auto", 2 * n_cu, "hardest_first", True),
+             tune.Schedule("auto", 2 * n_cu, "unsat_first", True)]
     best = tune.tune(code.base, code.z, fr.syn, fr.llr, max_iter, difficulty=fr.qber, cache_path=None, cands=cands,
                      reps=2)
     sched = tune.Schedule(**best["schedule"])

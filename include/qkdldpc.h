@@ -220,6 +220,23 @@ int ldpc_batch_create(const ldpc_code *code, const uint8_t *syndromes, const int
 int ldpc_batch_launch(ldpc_batch *batch, void *stream);
 void ldpc_batch_destroy(ldpc_batch *batch);
 
+/* Decode order for a persistent schedule (ldpc_schedule.order): frames whose
+ * channel hard decision y^ = [llr < 0] fails more check rows first. Sec. 2
+ * tests H x^ = s to stop; applied to y^ before any iteration, the number of
+ * failing rows grows with the number of channel errors and predicts how many
+ * iterations a frame needs, so decoding those frames first shortens a batch's
+ * tail. The order never changes a frame's result.
+ * syndromes: DEVICE uint8 [n_frames][ceil(m/8)]; llr_in: DEVICE int8 [n_frames][n].
+ * out_unsat: DEVICE int32 [n_frames]: the number of rows i with (H y^)_i != s_i.
+ * out_order: DEVICE int32 [n_frames] or NULL: a permutation of 0..n_frames-1 by
+ *            decreasing out_unsat, in buckets of 2^k counts (k the smallest with
+ *            m >> k < 1024); the order inside a bucket is unspecified.
+ * Uses no workspace and allocates nothing; asynchronous on stream. Returns
+ * LDPC_EINVAL for NULL arguments or n_frames < 0 (0 is a no-op), LDPC_EDEVICE
+ * for launch failures. */
+int ldpc_order_by_unsat(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
+                        int32_t n_frames, int32_t *out_unsat, int32_t *out_order, void *stream);
+
 /* Alice's side of the syndrome exchange: out_syn = H bits for a batch.
  * bits: DEVICE uint8 [n_frames][ceil(n/8)] packed; out_syn: DEVICE uint8
  * [n_frames][ceil(m/8)] packed. */

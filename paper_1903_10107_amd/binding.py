@@ -94,6 +94,8 @@ def lib():
         L.ldpc_batch_destroy.argtypes = [vp]
         L.ldpc_syndrome_batch.restype = C.c_int
         L.ldpc_syndrome_batch.argtypes = [vp, vp, i32, vp, vp]
+        L.ldpc_order_by_unsat.restype = C.c_int
+        L.ldpc_order_by_unsat.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.ldpc_probe_lds_bandwidth.restype = C.c_int
         L.ldpc_probe_lds_bandwidth.argtypes = [i32, i32, i32, vp, vp]
         L.ldpc_last_error.restype = C.c_char_p
@@ -350,6 +352,20 @@ def ldpc_syndrome_batch(code: Code, bits, n_frames: int, out_syn, stream=None):
     p_b = _dev_ptr(bits, torch.uint8, (F, (code.n + 7) // 8), "bits")
     p_s = _dev_ptr(out_syn, torch.uint8, (F, (code.m + 7) // 8), "out_syn")
     _check(lib().ldpc_syndrome_batch(code.handle, p_b, F, p_s, _stream_ptr(stream)))
+
+
+def ldpc_order_by_unsat(code: Code, syndromes, llr_in, n_frames: int, out_unsat, out_order=None, stream=None):
+    import torch
+    F = int(n_frames)
+    if F <= 0:
+        if F < 0:
+            raise ValueError("n_frames < 0")
+        return
+    p_s = _dev_ptr(syndromes, torch.uint8, (F, (code.m + 7) // 8), "syndromes")
+    p_l = _dev_ptr(llr_in, torch.int8, (F, code.n), "llr_in")
+    p_w = _dev_ptr(out_unsat, torch.int32, (F,), "out_unsat")
+    p_o = _dev_ptr(out_order, torch.int32, (F,), "out_order") if out_order is not None else None
+    _check(lib().ldpc_order_by_unsat(code.handle, p_s, p_l, F, p_w, p_o, _stream_ptr(stream)))
 
 
 def decode(code: Code, syn, llr, max_iter: int, *, want_state: bool = False, device: str = "cuda"):

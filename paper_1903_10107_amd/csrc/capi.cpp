@@ -799,6 +799,27 @@ void ldpc_batch_destroy(ldpc_batch *batch)
     delete batch;
 }
 
+int ldpc_order_by_unsat(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in, int32_t n_frames,
+                        int32_t *out_unsat, int32_t *out_order, void *stream)
+{
+    if (!code)
+        return fail(LDPC_EINVAL, "ldpc_order_by_unsat: code is NULL");
+    if (n_frames < 0)
+        return fail(LDPC_EINVAL, "ldpc_order_by_unsat: n_frames < 0");
+    if (n_frames == 0)
+        return LDPC_OK;
+    if (!syndromes || !llr_in || !out_unsat)
+        return fail(LDPC_EINVAL, "ldpc_order_by_unsat: syndromes, llr_in and out_unsat must be non-NULL");
+    int rc = check_device(code);
+    if (rc != LDPC_OK)
+        return rc;
+    hipError_t e = qkdldpc::launch_order_by_unsat(code->dev, syndromes, llr_in, n_frames, out_unsat, out_order,
+                                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail("ldpc_order_by_unsat: kernel launch", e);
+    return LDPC_OK;
+}
+
 int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames, uint8_t *out_syn,
                         void *stream)
 {

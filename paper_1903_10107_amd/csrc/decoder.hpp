@@ -65,6 +65,10 @@ hipError_t launch_multi_tail(const LaunchPlan &P, const DevCode &C, const Decode
 // per workgroup, out[n_workgroups * 1024]
 hipError_t launch_probe_lds(int mode, int n_workgroups, int reps, uint32_t *out, hipStream_t s);
 hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, uint8_t *out_syn, hipStream_t s);
+// per-frame count of check rows the channel hard decision fails, and (when
+// out_order is not null) the frames by decreasing count
+hipError_t launch_order_by_unsat(const DevCode &C, const uint8_t *syn, const int8_t *llr, int n_frames,
+                                 int32_t *out_w, int32_t *out_order, hipStream_t s);
 hipError_t launch_queue_reset(int *queue, hipStream_t s);
 hipError_t launch_reveal(int8_t *llr, int n, int n_frames, const int32_t *frame_ids, int k, const int32_t *positions,
                          const uint8_t *values, int r, hipStream_t s);

@@ -6,9 +6,11 @@ a representative batch held on the GPU and keeps the fastest:
 * kernel family (ldpc_params.kernel_hint): every family that applies to the code;
 * persistent workgroups: 0 (one workgroup per frame, hardware dispatch) or a
   multiple of the CU count pulling frames from a device queue;
-* decode order (persistent schedules only): as given, or hardest first by a
+* decode order (persistent schedules only): as given; hardest first by a
   per-frame difficulty the caller supplies (for instance the frame's QBER or
-  its expected iteration count), which moves long frames away from the end of
+  its expected iteration count); or by the number of check rows the channel
+  hard decision fails, computed on the GPU before every decode
+  (ldpc_order_by_unsat). The last two move long frames away from the end of
   the launch;
 * graph: the decode captured once as a HIP graph and replayed, or launched
   directly;
@@ -39,7 +41,7 @@ DEFAULT_CACHE = os.environ.get("QKDLDPC_TUNE_CACHE",
 class Schedule:
     kernel: str = "auto"
     persistent_workgroups: int = 0
-    order: str = "none"          # "none" or "hardest_first"
+    order: str = "none"          # "none", "hardest_first" (caller's difficulty) or "unsat_first"
     graph: bool = False
     check_every: int = 0         # layer-synchronous family: iterations between host checks (0: none)
 
@@ -62,7 +64,7 @@ def candidates(n_cu: int, has_difficulty: bool) -> list[Schedule]:
         out.append(Schedule("layer_sync", 0, "none", graph, 1))
     for kernel in B.PERSISTENT_FAMILIES:
         for wgs in (n_cu, 2 * n_cu):
-            for order in (("none", "hardest_first") if has_difficulty else ("none",)):
+            for order in (("none", "hardest_first", "unsat_first") if has_difficulty else ("none", "unsat_first")):
                 for graph in (False, True):
                     out.append(Schedule(kernel, wgs, order, graph))
     return out
@@ -84,9 +86,14 @@ class Runner:
         self.conv = torch.zeros(F, dtype=torch.uint8, device="cuda")
         self.iters = torch.zeros(F, dtype=torch.int32, device="cuda")
         self.order = None
+        self.unsat = None
         if sched.order == "hardest_first" and difficulty is not None:
             perm = np.argsort(-np.asarray(difficulty, dtype=np.float64), kind="stable").astype(np.int32)
             self.order = torch.from_numpy(perm).cuda()
+        elif sched.order == "unsat_first" and sched.persistent_workgroups:
+            # filled on the device before every decode (part of the timed step)
+            self.unsat = torch.empty(F, dtype=torch.int32, device="cuda")
+            self.order = torch.arange(F, dtype=torch.int32, device="cuda")
         need = B.ldpc_workspace_bytes_sched(self.code, F, sched.persistent_workgroups)
         self.ws = torch.empty(need, dtype=torch.uint8, device="cuda") if need else None
         self.sched = sched
@@ -97,6 +104,8 @@ class Runner:
                                  sched.persistent_workgroups, self.order, self.ws, check_every=sched.check_every)
 
     def __call__(self):
+        if self.unsat is not None:
+            B.ldpc_order_by_unsat(self.code, self.syn, self.llr, self.F, self.unsat, self.order)
         if self.batch is not None:
             self.batch.launch()
         else:
