@@ -236,6 +236,14 @@ def batched(wl, code, n_short, n_frames, steps, warmup):
             "undetected_errors": int(undetected.sum()), "mean_iters": round(float(iters.mean()), 3)}
 
 
+def batched_headline(n_frames, steps, warmup):
+    """The batched figure on the headline workload (for profiling it alone)."""
+    from paper_1903_10107_amd import inputs as I
+    wl = I.WORKLOADS["n32768_q2"]
+    code = wl.code()
+    return batched(wl, code, int(round(wl.short_frac * code.n)), n_frames, steps, warmup)
+
+
 def ragged(n_frames, steps, warmup):
     """Ragged batch of the rate-adaptive mother code (24x48 base, Z = 2048,
     n = 98304, R = 1/2): each frame's QBER is drawn from {1, 2, 4, 6, 8}% and
@@ -641,7 +649,7 @@ def main():
     ap.add_argument("--qber-sweep", default="",
                     help="comma-separated QBERs for --fer-sweep (default: the workload's)")
     ap.add_argument("--sweep-frames", type=int, default=4096)
-    ap.add_argument("--only", choices=("learned", "syndrome", "retry", "large"), default=None,
+    ap.add_argument("--only", choices=("learned", "syndrome", "retry", "large", "batched", "ragged"), default=None,
                     help="run one figure alone and print it as one JSON line (for profiling its kernels)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="instead of decoding, run a plain device copy of BYTES bytes per step "
@@ -666,7 +674,9 @@ def main():
         fig = {"learned": lambda: learned(args.learned_steps, args.steps, args.warmup),
                "syndrome": lambda: syndrome_figure(args.syndrome_frames, args.steps, args.warmup),
                "retry": lambda: retry_figure(args.retry_frames),
-               "large": lambda: large_frames(args.steps, args.warmup)}[args.only]()
+               "large": lambda: large_frames(args.steps, args.warmup),
+               "batched": lambda: batched_headline(args.batched_frames, args.steps, args.warmup),
+               "ragged": lambda: ragged(args.ragged_frames, args.steps, args.warmup)}[args.only]()
         print(json.dumps({"figure": args.only, args.only: fig}), flush=True)
         return
     if args.workload == "n98304_ragged":

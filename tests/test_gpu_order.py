@@ -55,10 +55,12 @@ def _bucket_shift(m):
 
 
 @pytest.mark.parametrize("mb,nb,z,F,q,short", [
-    (5, 32, 1024, 300, 0.02, 0.33),    # the headline code, several buckets per count range
+    (5, 32, 1024, 300, 0.02, 0.33),    # the headline code (word-parallel counts), several buckets
     (4, 12, 37, 64, 0.05, 0.0),        # odd Z, n not a multiple of 64
     (10, 64, 16384, 4, 0.02, 0.0),     # n = 2^20: 128 KB of sign bits in LDS
     (5, 32, 32, 2500, 0.03, 0.0),      # more frames than the order kernel's threads
+    (5, 32, 48, 40, 0.03, 0.0),        # Z not a multiple of 32, n is: one lane per row, 16-byte sign loads
+    (10, 64, 32768, 2, 0.02, 0.0),     # n = 2^21: the sign words do not fit in LDS
 ])
 def test_unsat_counts_and_order(B, mb, nb, z, F, q, short):
     import torch
