@@ -780,7 +780,12 @@ def main():
                                         "frac": round(achieved / HBM_PEAK_GBS, 4),
                                         "algorithmic_bytes_per_launch": alg_bytes,
                                         "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration x "
-                                                      f"{edge_iters:.0f} edge-iterations + {io_bytes} B frame I/O"}},
+                                                      f"{edge_iters:.0f} edge-iterations + {io_bytes} B frame I/O"},
+                     # one frame per CU: the launch lasts as long as its slowest frame, so
+                     # the CUs of the other frames idle for the rest of it
+                     "tail": {"frames": F, "cus": torch.cuda.get_device_properties(0).multi_processor_count,
+                              "mean_iters": round(float(iters.mean()), 3), "max_iters": int(iters.max()),
+                              "cu_busy_frac": round(float(iters.mean()) / max(int(iters.max()), 1), 4)}},
         "fer": round(fails / F, 5),
         "fer_ci95": [round(v, 5) for v in M.wilson_interval(fails, F)],
         "undetected_errors": int(undetected.sum()),
