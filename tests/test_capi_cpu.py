@@ -102,6 +102,8 @@ def test_null_out_and_null_code_are_rejected():
                                         None) == B.LDPC_EINVAL
     assert B.lib().ldpc_code_dims(None, None, None, None, None, None) == B.LDPC_EINVAL
     assert B.lib().ldpc_syndrome_batch(None, None, 1, None, None) == B.LDPC_EINVAL
+    assert B.lib().ldpc_order_by_unsat(None, None, None, 1, None, None, None) == B.LDPC_EINVAL
+    assert b"code is NULL" in B.lib().ldpc_last_error()
     assert B.lib().ldpc_workspace_bytes(None, 4) == 0
     B.lib().ldpc_code_destroy(None)
 
