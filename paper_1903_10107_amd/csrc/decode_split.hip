@@ -125,7 +125,9 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             }
             return u;
         };
-        conv = !block_vote(unsat_range(0, C.mb), flags, vk);
+        // layer 0 first: a frame that fails there (nearly every frame before its
+        // first iteration) skips testing the other layers
+        conv = !block_vote(unsat_range(0, 1), flags, vk) && !block_vote(unsat_range(1, C.mb), flags, vk);
         // Each lane keeps its row pairs' syndrome bits in registers (this path
         // takes at most 32 layers): word b / 16, bit b % 16 for row b*Z + r and
         // bit 16 + b % 16 for row b*Z + r + Z/2; layer b's pair (the sign bits
@@ -306,7 +308,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             __syncthreads();
         }
         if (!conv && A.max_iter > 0)
-            conv = !block_vote(unsat_range(0, C.mb), flags, vk);
+            conv = !block_vote(unsat_range(0, 1), flags, vk) && !block_vote(unsat_range(1, C.mb), flags, vk);
     } else {
         // more row pairs than that: separate check after every iteration
         auto unsat_all = [&]() {
