@@ -216,9 +216,10 @@ def batched(wl, code, n_short, n_frames, steps, warmup):
 
     fr = I.make_frames(code, n_frames, wl.qber, 10107, n_short=n_short)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    cands = [tune.Schedule("auto", 0, "none", False), tune.Schedule("split", n_cu, "none", False),
-             tune.Schedule("split", 2 * n_cu, "none", False), tune.Schedule("split", 2 * n_cu, "none", True),
-             tune.Schedule("split", n_cu, "unsat_first", True), tune.Schedule("split", 2 * n_cu, "unsat_first", True)]
+    cands = [tune.Schedule("auto", 0, "none", False)]
+    for fam in ("split_reg", "split"):
+        cands += [tune.Schedule(fam, n_cu, "none", False), tune.Schedule(fam, 2 * n_cu, "none", True),
+                  tune.Schedule(fam, n_cu, "unsat_first", True), tune.Schedule(fam, 2 * n_cu, "unsat_first", True)]
     best = tune.tune(code.base, code.z, fr.syn, fr.llr, wl.max_iter, acc_bits=wl.acc_bits, cache_path=None,
                      cands=cands, reps=2)
     sched = tune.Schedule(**best["schedule"])

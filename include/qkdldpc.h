@@ -68,7 +68,8 @@ typedef struct {
                                subtracted from every CN message magnitude at iteration t using
                                row min(t-1, offset_iters-1), result clamped to [0, msg_max];
                                copied at create. NULL = no offsets (the paper's decoder).
-                               Every kernel family serves them. */
+                               Every kernel family but LDPC_KERNEL_SPLIT_REG serves them
+                               (automatic selection then takes the next family). */
     int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
     int32_t kernel_hint;    /* 0: pick the kernel family automatically; LDPC_HINT_*: use that
                                family, or fail with LDPC_EUNSUPPORTED when it does not apply
@@ -82,7 +83,8 @@ enum {
     LDPC_HINT_PAIRS = 3,
     LDPC_HINT_SPLIT = 4,
     LDPC_HINT_SPLIT_GLOBAL_L = 5,
-    LDPC_HINT_LAYER_SYNC = 6
+    LDPC_HINT_LAYER_SYNC = 6,
+    LDPC_HINT_SPLIT_REG = 7
 };
 
 /* Build a code from a quasi-cyclic base matrix (Sec. 4.1).
@@ -142,13 +144,18 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
  * LDPC_KERNEL_SPLIT_GLOBAL_L  as LDPC_KERNEL_SPLIT with E in LDS and the CN
  *                      messages L in a global-memory slice per workgroup (codes
  *                      whose L does not fit in LDS beside E).
+ * LDPC_KERNEL_SPLIT_REG  as LDPC_KERNEL_SPLIT with the CN messages L of every
+ *                      layer held in registers for the whole decode and E in
+ *                      LDS (codes of five base rows, power-of-two z <= 1024,
+ *                      rows of 19 or 20 edges, 8-bit soft values with
+ *                      e_max > msg_max, no offset table).
  * LDPC_KERNEL_LAYER_SYNC  one launch per layer over all frames, several
  *                      workgroups per frame, E and L in global slices per frame
  *                      (codes whose soft values do not fit in LDS, e.g. n = 2^20);
  *                      the decode is a sequence of launches on the stream; at
  *                      most 65535 frames per decode call (LDPC_EINVAL above).
- * Automatic selection prefers them in the order SPLIT, SPLIT_GLOBAL_L,
- * LAYER_SYNC, PAIRS, LDS, GLOBAL, taking the first that applies. Also the
+ * Automatic selection prefers them in the order SPLIT_REG, SPLIT,
+ * SPLIT_GLOBAL_L, LAYER_SYNC, PAIRS, LDS, GLOBAL, taking the first that applies. Also the
  * workgroup size and the dynamic LDS bytes per workgroup. Any output pointer may
  * be NULL. */
 enum {
@@ -157,7 +164,8 @@ enum {
     LDPC_KERNEL_PAIRS = 2,
     LDPC_KERNEL_SPLIT = 3,
     LDPC_KERNEL_SPLIT_GLOBAL_L = 4,
-    LDPC_KERNEL_LAYER_SYNC = 5
+    LDPC_KERNEL_LAYER_SYNC = 5,
+    LDPC_KERNEL_SPLIT_REG = 6
 };
 int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int32_t *lds_bytes);
 
@@ -171,7 +179,7 @@ typedef struct {
     int32_t persistent_workgroups; /* > 0: launch that many workgroups; each takes the next
                                       frame from a device queue until none is left, so a CU that
                                       finishes a frame starts another at once. Needs the
-                                      LDPC_KERNEL_SPLIT or LDPC_KERNEL_SPLIT_GLOBAL_L kernel
+                                      LDPC_KERNEL_SPLIT_REG, LDPC_KERNEL_SPLIT or LDPC_KERNEL_SPLIT_GLOBAL_L kernel
                                       family (ldpc_code_plan); the latter's workspace then
                                       holds one L slice per workgroup instead of per frame. */
     const int32_t *order;          /* DEVICE int32 [n_frames] or NULL: the order in which the

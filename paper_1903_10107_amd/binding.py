@@ -28,9 +28,11 @@ LDPC_RULE_RCBP_FB = 0
 LDPC_RULE_RCBP_EQ7 = 1
 LDPC_RULE_MINSUM = 2
 
-KERNEL_NAMES = {0: "global", 1: "lds", 2: "pairs", 3: "split", 4: "split_global_l", 5: "layer_sync"}
-KERNEL_HINTS = {"auto": 0, "global": 1, "lds": 2, "pairs": 3, "split": 4, "split_global_l": 5, "layer_sync": 6}
-PERSISTENT_FAMILIES = ("split", "split_global_l")
+KERNEL_NAMES = {0: "global", 1: "lds", 2: "pairs", 3: "split", 4: "split_global_l", 5: "layer_sync",
+                6: "split_reg"}
+KERNEL_HINTS = {"auto": 0, "global": 1, "lds": 2, "pairs": 3, "split": 4, "split_global_l": 5, "layer_sync": 6,
+                "split_reg": 7}
+PERSISTENT_FAMILIES = ("split_reg", "split", "split_global_l")
 
 
 class LdpcError(RuntimeError):

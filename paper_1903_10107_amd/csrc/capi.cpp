@@ -110,6 +110,42 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     const bool split_ok = P.pow2 && h.z >= 2 && h.max_deg <= 20 &&
                           (h.cn_rule == LDPC_RULE_RCBP_FB || h.cn_rule == LDPC_RULE_MINSUM);
     const int dmax = (h.min_deg == 6 && h.max_deg == 6) ? 6 : h.max_deg <= 8 ? 8 : 20, dh = dmax / 2;
+    P.split_reg = false;
+    // Split arithmetic with L in registers: five base rows, rows of 19 or 20 edges
+    // (DMAX = 20), 8-bit soft values with E_max > MSG_max (the frozen test
+    // relies on a frozen E and its Eq. 8 value sharing a sign), no offset
+    // table, one lane pair per row
+    // pair (Z <= 1024), E byte addresses below 2^16. LDS: E plus the dummy block
+    // column, the syndrome, the per-lane address table [threads][mb][dh] of
+    // 16-bit entries, three vote words and the queue slot.
+    if ((hint == 0 || hint == LDPC_HINT_SPLIT_REG) && split_ok && h.mb == 5 && dmax == 20 && h.min_deg >= 19 &&
+        h.acc_bits == 8 && h.e_max > h.msg_max &&
+        h.offsets.empty() && h.z <= 1024 && (size_t)h.n + h.z <= 65536) {
+        const int threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
+        const size_t e_sp = round_up((size_t)h.n + h.z, 16);
+        const size_t tab = round_up((size_t)h.mb * dh * threads * 2, 16);
+        const size_t total = e_sp + round_up(syn_bytes, 16) + tab + 16;
+        if (total <= (size_t)lds_limit) {
+            P.split_reg = true;
+            P.split_dmax = dmax;
+            P.split_global_l = false;
+            P.layer_sync = false;
+            P.lds_state = true;
+            P.lds_bytes = total;
+            P.threads = threads;
+            c->l_stride = 0;
+            c->lds_l_off = 0;
+            c->lds_syn_off = (int)e_sp;
+            c->lds_tab_off = (int)(e_sp + round_up(syn_bytes, 16));
+            c->lds_flag_off = (int)(c->lds_tab_off + tab);
+            c->ws_l_off = 0;
+            c->ws_frame_bytes = 0;
+            c->lane_tab_bytes = (size_t)h.mb * dh * 2 * 16;
+            return true;
+        }
+    }
+    if (hint == LDPC_HINT_SPLIT_REG)
+        return false;
     if ((hint == 0 || split_hint) && split_ok) {
         const size_t e_sp = round_up(((size_t)h.n + h.z) * esize, 16);
         const size_t stride = (((size_t)h.mb * dh) | 1) * 4;
@@ -616,6 +652,7 @@ int ldpc_code_plan(const ldpc_code *code, int32_t *kernel, int32_t *threads, int
     const LaunchPlan &P = code->plan;
     if (kernel)
         *kernel = P.layer_sync  ? LDPC_KERNEL_LAYER_SYNC
+                  : P.split_reg  ? LDPC_KERNEL_SPLIT_REG
                   : P.split_dmax ? (P.split_global_l ? LDPC_KERNEL_SPLIT_GLOBAL_L : LDPC_KERNEL_SPLIT)
                   : P.pairs    ? LDPC_KERNEL_PAIRS
                   : P.lds_state ? LDPC_KERNEL_LDS

@@ -47,6 +47,7 @@ struct LaunchPlan {
     int split_dmax;   // split kernel (two lanes per row pair) with this slot count, or 0
     bool split_global_l; // split kernel with L in a global slice per workgroup (E stays in LDS)
     bool layer_sync;  // one launch per layer over all frames, E and L in global slices per frame
+    bool split_reg;   // split arithmetic with L in registers (five base rows, 8-bit E, no offsets)
     size_t lds_bytes; // dynamic LDS per workgroup
 };
 
@@ -54,6 +55,7 @@ hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs
 hipError_t launch_decode_scalar(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+hipError_t launch_decode_reg(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 // The layer-synchronous decode in three phases, for callers that stop early:
 // stage-in and the iteration-0 check; iterations t0..t1; stage-out.

@@ -141,7 +141,7 @@ int build_host_code(const int32_t *base, int32_t mb, int32_t nb, int32_t z, cons
         err = "ldpc_code_create: offset_iters given without offsets";
         return LDPC_EINVAL;
     }
-    if (prm.kernel_hint < 0 || prm.kernel_hint > LDPC_HINT_LAYER_SYNC) {
+    if (prm.kernel_hint < 0 || prm.kernel_hint > LDPC_HINT_SPLIT_REG) {
         err = fmt("ldpc_code_create: unknown kernel_hint %ld", prm.kernel_hint);
         return LDPC_EINVAL;
     }

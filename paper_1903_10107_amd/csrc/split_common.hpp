@@ -229,6 +229,46 @@ struct LdsESink {
     }
 };
 
+// Check-node magnitudes of a row pair whose DMAX = 2 DH operands are split over
+// the two lanes of a pair (lane A: edges 0 .. DH-1, lane B: edges DMAX-1 .. DH):
+// min-sum, or Eq. 4 by Alg. 1 in forward-backward order. Lane A's left fold over
+// its slots gives the forward partials, lane B's the backward ones; one lane
+// swap hands each lane the other's last partial, and each lane's outputs are
+// out_i = tau(X_{i-1}, W_{DH-1-i}) with out_0 = W_{DH-1}.
+template <int DH, int RULE>
+__device__ __forceinline__ void pair_fold(const u16x2 (&p)[DH], u16x2 (&out)[DH])
+{
+    if constexpr (RULE == kRuleMinSum) {
+        u16x2 m1 = usplat2(0x7fff), m2 = usplat2(0x7fff);
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            m2 = umin2(m2, umax2(m1, p[i]));
+            m1 = umin2(m1, p[i]);
+        }
+        const u16x2 o1 = swap_pair(m1), o2 = swap_pair(m2);
+        m2 = umin2(umin2(m2, o2), umax2(m1, o1));
+        m1 = umin2(m1, o1);
+        const u16x2 diff = m2 - m1;
+#pragma unroll
+        for (int i = 0; i < DH; ++i)
+            out[i] = m2 - umin2(p[i] - m1, usplat2(1)) * diff;
+    } else {
+        u16x2 X[DH], W[DH];
+        X[0] = p[0];
+#pragma unroll
+        for (int i = 1; i < DH; ++i)
+            X[i] = tau2(X[i - 1], p[i]);
+        W[0] = swap_pair(X[DH - 1]);
+#pragma unroll
+        for (int k = 1; k < DH; ++k)
+            W[k] = tau2(W[k - 1], p[DH - k]);
+        out[0] = W[DH - 1];
+#pragma unroll
+        for (int i = 1; i < DH; ++i)
+            out[i] = tau2(X[i - 1], W[DH - 1 - i]);
+    }
+}
+
 // Eq. 8, the check node (Eqs. 1, 4 by Alg. 1, or min-sum) and Eq. 9 under Alg. 2
 // for one lane's slots of a row pair; the new soft values go to es(a0, value),
 // the new messages to Lr.
@@ -241,7 +281,7 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
     const s16x2 em = splat2(C.e_max), em1 = splat2(C.e_max - 1);
     const u16x2 mm = usplat2(C.msg_max);
     s16x2 v[DH];
-    u16x2 p[DH], X[DH], W[DH];
+    u16x2 p[DH];
     s16x2 own = splat2(0);
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
@@ -260,34 +300,7 @@ __device__ __forceinline__ void split_finish(const DevCode &C, const SplitRow<DM
     // sign product of Eq. 1 over the whole row, times the syndrome bit
     const s16x2 par = syn ^ own ^ swap_pair(own);
     u16x2 out[DH];
-    if constexpr (RULE == kRuleMinSum) {
-        u16x2 m1 = usplat2(0x7fff), m2 = usplat2(0x7fff);
-#pragma unroll
-        for (int i = 0; i < DH; ++i) {
-            m2 = umin2(m2, umax2(m1, p[i]));
-            m1 = umin2(m1, p[i]);
-        }
-        const u16x2 o1 = swap_pair(m1), o2 = swap_pair(m2);
-        m2 = umin2(umin2(m2, o2), umax2(m1, o1));
-        m1 = umin2(m1, o1);
-        const u16x2 diff = m2 - m1;
-#pragma unroll
-        for (int i = 0; i < DH; ++i)
-            out[i] = m2 - umin2(p[i] - m1, usplat2(1)) * diff;
-    } else {
-        X[0] = p[0];
-#pragma unroll
-        for (int i = 1; i < DH; ++i)
-            X[i] = tau2(X[i - 1], p[i]);
-        W[0] = swap_pair(X[DH - 1]);
-#pragma unroll
-        for (int k = 1; k < DH; ++k)
-            W[k] = tau2(W[k - 1], p[DH - k]);
-        out[0] = W[DH - 1];
-#pragma unroll
-        for (int i = 1; i < DH; ++i)
-            out[i] = tau2(X[i - 1], W[DH - 1 - i]);
-    }
+    pair_fold<DH, RULE>(p, out);
     if constexpr (OFF) {
         // offset table: magnitude = clamp(mag - offset, 0, MSG_max) (both halves share the block)
 #pragma unroll

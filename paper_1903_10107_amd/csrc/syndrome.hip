@@ -180,6 +180,8 @@ hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs
 {
     if (P.layer_sync)
         return launch_decode_multi(P, C, A, s);
+    if (P.split_reg)
+        return launch_decode_reg(P, C, A, s);
     if (P.split_dmax)
         return launch_decode_split(P, C, A, s);
     if (P.pairs)

@@ -57,7 +57,7 @@ def _key(base, z, n_frames, max_iter, acc_bits, has_difficulty) -> str:
 
 def candidates(n_cu: int, has_difficulty: bool) -> list[Schedule]:
     out = []
-    for kernel in ("split", "split_global_l", "layer_sync", "pairs", "lds", "global"):
+    for kernel in ("split_reg", "split", "split_global_l", "layer_sync", "pairs", "lds", "global"):
         out.append(Schedule(kernel, 0, "none", False))
         out.append(Schedule(kernel, 0, "none", True))
     for graph in (False, True):

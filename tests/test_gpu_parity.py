@@ -146,7 +146,7 @@ def test_cases_cover_every_kernel_family(B):
         if ckw.get("offsets") in ("rand", "rand_signed"):
             ckw["offsets"] = np.zeros((1, int((mk() >= 0).sum())), np.int8)
         seen.add(B.Code(mk(), z, **ckw).plan()["kernel"])
-    assert seen == {"global", "lds", "pairs", "split", "split_global_l", "layer_sync"}, seen
+    assert seen == {"global", "lds", "pairs", "split", "split_global_l", "layer_sync", "split_reg"}, seen
 
 
 def test_llr_minus_128_is_read_as_minus_127(B):
@@ -241,7 +241,7 @@ def test_parity_full_n1048576_sampled(B):
     _full_size(B, "n1048576_q2", sample=np.array([0, 31]))
 
 
-@pytest.mark.parametrize("kernel", ["split", "pairs", "global", "layer_sync"])
+@pytest.mark.parametrize("kernel", ["split_reg", "split", "pairs", "global", "layer_sync"])
 @pytest.mark.parametrize("mode", ["saturated", "zero", "small"])
 def test_degenerate_channel_values(B, mode, kernel):
     """Soft inputs at the edges of the method: every |E| = E_max from the start

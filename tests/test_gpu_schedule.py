@@ -228,8 +228,8 @@ def test_early_stop_all_converged_at_iteration_0_and_argument_errors(B):
     with pytest.raises(B.LdpcError) as ei:
         B.ldpc_decode_batch_sched(gc, syn, llr, 4, 20, bits, conv, iters, check_every=-1)
     assert ei.value.code == B.LDPC_EINVAL
-    sp = B.Code(code.base, code.z)                # split family: check_every is ignored
-    assert sp.plan()["kernel"] == "split"
+    sp = B.Code(code.base, code.z)                # single-launch family: check_every is ignored
+    assert sp.plan()["kernel"] in ("split_reg", "split")
     B.ldpc_decode_batch_sched(sp, syn, llr, 4, 20, bits, conv, iters, check_every=2)
     torch.cuda.synchronize()
     assert np.array_equal(bits.cpu().numpy(), ref["bits"])
