@@ -209,6 +209,26 @@ int ldpc_decode_batch_sched(const ldpc_code *code, const uint8_t *syndromes, con
                             void *workspace, size_t workspace_bytes, void *stream);
 size_t ldpc_workspace_bytes_sched(const ldpc_code *code, int32_t n_frames, const ldpc_schedule *sched);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decode as ldpc_decode_batch_sched, with the workspace taken from a static
+ * device buffer of LDPC_STATIC_WORKSPACE_BYTES that the library holds on every
+ * device it runs on until the process ends. No call allocates or frees device
+ * memory. Arguments and results are those of ldpc_decode_batch_sched without
+ * the workspace arguments.
+ * Errors: LDPC_EINVAL when ldpc_workspace_bytes_sched(code, n_frames, sched)
+ * exceeds LDPC_STATIC_WORKSPACE_BYTES (decode fewer frames per call, or use a
+ * persistent schedule, whose workspace does not grow with the frames);
+ * LDPC_EUNSUPPORTED for sched->check_every > 0 (that schedule reads a count back
+ * to the host). All calls on one device share its buffer, which keeps the last
+ * call's contents: two calls that overlap on one device (different streams, or
+ * different host threads) race and must be ordered by the caller. */
+#define LDPC_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int ldpc_decode_batch_static(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
+                             int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
+                             uint8_t *out_converged, int32_t *out_iters, const ldpc_schedule *sched,
+                             void *stream);
+
 /* A decode of fixed buffers captured once as a HIP graph (the queue reset and the
  * decode kernel), replayed by ldpc_batch_launch with one graph launch. With
  * sched->check_every = k > 0 on the layer-synchronous family the batch holds a

@@ -85,6 +85,8 @@ def lib():
         L.ldpc_decode_batch_sched.restype = C.c_int
         L.ldpc_decode_batch_sched.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(ldpc_schedule), vp,
                                               C.c_size_t, vp]
+        L.ldpc_decode_batch_static.restype = C.c_int
+        L.ldpc_decode_batch_static.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(ldpc_schedule), vp]
         L.ldpc_workspace_bytes_sched.restype = C.c_size_t
         L.ldpc_workspace_bytes_sched.argtypes = [vp, i32, C.POINTER(ldpc_schedule)]
         L.ldpc_batch_create.restype = C.c_int
@@ -307,6 +309,31 @@ def ldpc_decode_batch_sched(code: Code, syndromes, llr_in, n_frames: int, max_it
         ws_bytes = workspace.numel()
     _check(lib().ldpc_decode_batch_sched(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, p_it,
                                          C.byref(sch), p_ws, ws_bytes, _stream_ptr(stream)))
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20   # LDPC_STATIC_WORKSPACE_BYTES
+
+
+def ldpc_decode_batch_static(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
+                             out_iters=None, persistent_workgroups: int = 0, order=None, stream=None,
+                             check_every: int = 0):
+    """ldpc_decode_batch_sched with the library's static workspace (no device
+    allocation by the library or here)."""
+    import torch
+    F = int(n_frames)
+    if F < 0:
+        raise ValueError("n_frames < 0")
+    if F == 0:
+        return
+    sb, bb = (code.m + 7) // 8, (code.n + 7) // 8
+    p_syn = _dev_ptr(syndromes, torch.uint8, (F, sb), "syndromes")
+    p_llr = _dev_ptr(llr_in, torch.int8, (F, code.n), "llr_in")
+    p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
+    p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
+    p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
+    sch = _schedule(F, persistent_workgroups, order, check_every)
+    _check(lib().ldpc_decode_batch_static(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, p_it,
+                                          C.byref(sch), _stream_ptr(stream)))
 
 
 class Batch:

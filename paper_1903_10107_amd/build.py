@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libqkdldpc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qc_code.cpp", "capi.cpp", "syndrome.hip", "decode_scalar.hip", "decode_pairs.hip", "decode_split.hip", "decode_reg.hip", "decode_multi.hip", "oms.hip", "probe.hip", "order.hip"]
+SOURCES = ["qc_code.cpp", "capi.cpp", "syndrome.hip", "decode_scalar.hip", "decode_pairs.hip", "decode_split.hip", "decode_reg.hip", "decode_multi.hip", "oms.hip", "probe.hip", "order.hip", "static_ws.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -43,6 +43,13 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+} // namespace
+
+// Error reporting for the library's other source files.
+int qkdldpc::set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+namespace {
+
 int hip_fail(const char *what, hipError_t e)
 {
     g_err = std::string(what) + ": " + hipGetErrorString(e);

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "qc_code.hpp"
 
@@ -50,6 +51,9 @@ struct LaunchPlan {
     bool split_reg;   // split arithmetic with L in registers (five base rows, 8-bit E, no offsets)
     size_t lds_bytes; // dynamic LDS per workgroup
 };
+
+// Set the thread's ldpc_last_error message; returns code.
+int set_error(int code, const std::string &msg);
 
 hipError_t launch_decode(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_scalar(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);

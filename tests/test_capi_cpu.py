@@ -159,3 +159,9 @@ def test_c_client_links_and_loads_without_a_gpu():
     assert os.path.exists(client), "build() builds tests/c_client/decode_client"
     out = subprocess.run([client], capture_output=True, text=True, timeout=60)
     assert out.returncode == 1 and "usage" in out.stderr, out.stderr
+
+
+def test_static_decode_rejects_a_null_code_without_a_gpu():
+    rc = B.lib().ldpc_decode_batch_static(None, None, None, 1, 5, None, None, None, None, None)
+    assert rc == B.LDPC_EINVAL
+    assert b"code is NULL" in B.lib().ldpc_last_error()
