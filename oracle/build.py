@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra",
+    cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra",
            "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -27,7 +27,7 @@
  *     which is not associative, uses the forward-backward order (rule 0); the
  *     literal right fold of Eq. 7 is rule 1; min-sum is rule 2.
  *
- * Build: gcc -O2 -fopenmp -shared -fPIC (see build.py beside this file).
+ * Build: gcc -O3 -fopenmp -shared -fPIC (see build.py beside this file).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -49,17 +49,28 @@ static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v
 /* ------------------------------------------------------------------------ */
 /* Check node: Alg. 1 (Sec. 3.2), the integer table tau(p, q) that stands for */
 /* beta((p + 1/2) Delta, (q + 1/2) Delta) of Eq. 6, computed by formula.       */
+/*                                                                            */
+/* Read as a correction: the box-plus of two magnitudes (each first clipped  */
+/* to msg_max) is the smaller one, lowered by one step for every closeness    */
+/* threshold that the gap between the two stays below, and never below 0.    */
+/* A smaller operand above 2 has the thresholds 2 and 6 (up to two steps); a  */
+/* smaller operand of 2 or less has the single threshold 4.                   */
 /* ------------------------------------------------------------------------ */
+static const int tau_gap_thresholds_large[] = {2, 6};
+static const int tau_gap_thresholds_small[] = {4};
+
 int oracle_tau(int p, int q, int msg_max)
 {
-    int a = imin(p, msg_max);
-    int b = imin(q, msg_max);
-    int g = imax(a, b);
-    int l = imin(a, b);
-    int d = g - l;
-    if (l > 2)
-        return l - (d < 2) - (d < 6);
-    return imax(l - (d < 4), 0);
+    const int lo = imin(imin(p, q), msg_max);
+    const int hi = imin(imax(p, q), msg_max);
+    const int gap = hi - lo;
+    const int *th = lo > 2 ? tau_gap_thresholds_large : tau_gap_thresholds_small;
+    const int n_th = lo > 2 ? 2 : 1;
+    int steps = 0;
+    for (int i = 0; i < n_th; i++)
+        if (gap < th[i])
+            steps++;
+    return imax(lo - steps, 0);
 }
 
 /* Degree-d box-plus of every "all operands but k" subset (Eq. 4), with tau as
