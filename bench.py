@@ -46,19 +46,30 @@ def algorithmic_int_ops(code_dims, iters_sum):
     n_edges = z * sum(degs)
     per_iter = 14 * n_edges + 27 * z * sum(d - 2 for d in degs)
     return float(per_iter) * float(iters_sum)
+# Least shortening of the n = 32768 code at QBER 2% with FER <= 1e-2: the
+# bisection of paper_1903_10107_amd.rate (2048 frames per probe, 256-position
+# steps) ends at 9720 shortened positions (29.7%).
+I_LEAST_SHORT = 9720
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1903_10107_amd", "csrc")
 
 
-# Sources the decode kernel of the headline workload (the split family) is compiled from.
-HEADLINE_KERNEL_SOURCES = ("decode_split.hip", "split_common.hpp", "kernels.hpp", "rcbp.hpp", "decoder.hpp",
-                           "qc_code.hpp")
+# Decode kernel of each family (the symbol rocprofv3 reports) and the sources it
+# is compiled from.
+KERNEL_SYMBOLS = {"split_reg": "k_decode_frame_reg", "split": "k_decode_frame_split",
+                  "split_global_l": "k_decode_frame_split", "pairs": "k_decode_frame_x2", "lds": "k_decode_frame",
+                  "global": "k_decode_frame", "layer_sync": "k_multi_layer"}
+KERNEL_SOURCES = {"split_reg": ("decode_reg.hip", "split_common.hpp", "kernels.hpp", "rcbp.hpp", "decoder.hpp",
+                                "qc_code.hpp"),
+                  "split": ("decode_split.hip", "split_common.hpp", "kernels.hpp", "rcbp.hpp", "decoder.hpp",
+                            "qc_code.hpp")}
+HEADLINE_FAMILY = "split_reg"
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(family: str = HEADLINE_FAMILY) -> str:
     """Hash of the sources the headline decode kernel is built from."""
     h = hashlib.sha256()
-    for name in HEADLINE_KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[family]:
         h.update(name.encode())
         h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
@@ -149,6 +160,7 @@ def cpu_baseline(code, fr, wl, seconds: float):
         ok1 += int(fr.key_bits()[sl][ok].sum())
         n1 += 1
     return {"value": round(bits_ok / elapsed / 1e6, 3), "unit": "Mbit/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "build": "gcc -O3, OpenMP over frames, no intrinsics",
             "sample": f"{done} frame decodes cycling over the {fr.n_frames} frames of the same workload "
                       f"(oracle, {threads} OpenMP threads over frames, {elapsed:.1f} s of decoding)",
             "single_thread": {"value": round(ok1 / t1 / 1e6, 3), "unit": "Mbit/s", "cores": 1,
@@ -308,6 +320,7 @@ def learned(steps_train, steps, warmup):
     from paper_1903_10107_amd import inputs as I
     from paper_1903_10107_amd import learn as LN
     from paper_1903_10107_amd import metrics as M
+    from paper_1903_10107_amd import rate
     from paper_1903_10107_amd import tune
 
     T, F, q = 20, 512, 0.02
@@ -364,15 +377,45 @@ def learned(steps_train, steps, warmup):
     fwd_bytes = float(B.ldpc_oms_tape_bytes(code_h, F, T)) + \
         F * (4.0 * code.n + (code.m + 7) // 8 + (code.n + 7) // 8)
     fwd_gbs = fwd_bytes / (fwd_ms / 1e3) / 1e9
+    # backward: reads the tape once (and the syndromes and target bits), writes the
+    # per-frame offset gradients [F][T][n_blocks]; 10 FP32 ops per edge-iteration
+    # (adjoint of Eq. 9, of the sign, of the clamp, the routing to the minimum or
+    # second minimum, the adjoint of Eq. 8 into E and L, the offset gradient)
+    bwd_bytes = float(B.ldpc_oms_tape_bytes(code_h, F, T)) + \
+        F * ((code.m + 7) // 8 + (code.n + 7) // 8 + 4.0 * T * code.n_blocks)
+    bwd_gbs = bwd_bytes / (bwd_ms / 1e3) / 1e9
+    bwd_tops = 10 * edge_iters / (bwd_ms / 1e3) / 1e12
 
     offsets = LN.int_offsets(bt.cpu().numpy())
-    judged = {}
-    for name, rule, off in (("rcbp", B.LDPC_RULE_RCBP_FB, None), ("minsum", B.LDPC_RULE_MINSUM, None),
-                            ("minsum_learned", B.LDPC_RULE_MINSUM, offsets)):
-        judged[name] = LN.evaluate(code, q, ns, max_iter=T, frames=4096, cn_rule=rule, offsets=off)
-    # throughput of the integer decoders on a 512-frame batch
+    decoders = (("rcbp", B.LDPC_RULE_RCBP_FB, None), ("minsum", B.LDPC_RULE_MINSUM, None),
+                ("minsum_learned", B.LDPC_RULE_MINSUM, offsets), ("rcbp_learned", B.LDPC_RULE_RCBP_FB, offsets))
+    # at the training rate (36% shortened) ...
+    judged = {name: LN.evaluate(code, q, ns, max_iter=T, frames=4096, cn_rule=rule, offsets=off)
+              for name, rule, off in decoders}
+    # ... and at equal frame error rate: each decoder at its own least shortening
+    # with FER <= 1e-2 (bisection on 2048 frames, 64-position steps), judged on
+    # 4096 fresh frames, with its throughput on a 512-frame batch there
+    equal_fer = {}
+    for name, rule, off in decoders:
+        op = rate.search(code, q, frames=2048, max_iter=T, fer_target=1e-2, step=64, seed=5151,
+                         cn_rule=rule, offsets=off)
+        ev = LN.evaluate(code, q, op.n_short, max_iter=T, frames=4096, seed=6161, cn_rule=rule, offsets=off)
+        fr = I.make_frames(code, F, q, 99, n_short=op.n_short)
+        run = tune.Runner(code.base, code.z, fr.syn, fr.llr, T, tune.Schedule(), None, 0, cn_rule=rule, offsets=off)
+        ms = tune.time_ms(run, max(3, steps // 5), max(1, warmup))
+        bits, conv, _ = run.outputs()
+        ok, _ = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
+        equal_fer[name] = {"shortened": op.n_short, "short_frac": round(op.n_short / code.n, 4),
+                           "bisection_fer": round(op.fer, 5), "fer": round(ev["fer"], 5),
+                           "fer_ci95": ev["fer_ci95"], "frames": ev["frames"], "undetected": ev["undetected"],
+                           "efficiency_f": round(ev["efficiency_f"], 4), "mean_iters": round(ev["mean_iters"], 3),
+                           "mbit_s": round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2),
+                           "ms_per_batch": round(ms, 4), "kernel": run.code.plan()["kernel"]}
+        print(f"[learned] {name}: {op.n_short} shortened, FER {ev['fer']:.4f}, f {ev['efficiency_f']:.3f}",
+              file=sys.stderr, flush=True)
+    # throughput of the integer decoders on a 512-frame batch at the training rate
     fr = I.make_frames(code, F, q, 99, n_short=ns)
-    for name, rule, off in (("rcbp", B.LDPC_RULE_RCBP_FB, None), ("minsum_learned", B.LDPC_RULE_MINSUM, offsets)):
+    for name, rule, off in decoders:
         run = tune.Runner(code.base, code.z, fr.syn, fr.llr, T, tune.Schedule(), None, 0, cn_rule=rule, offsets=off)
         ms = tune.time_ms(run, max(3, steps // 5), max(1, warmup))
         bits, conv, _ = run.outputs()
@@ -388,12 +431,26 @@ def learned(steps_train, steps, warmup):
                                  "unit": "TOP/s", "frac": round(fwd_tops / FP32_ALU_PEAK_TOPS, 4),
                                  "unit_ops": f"14 FP32 ops per edge-iteration x {edge_iters:.0f} edge-iterations",
                                  "fp32_vector_peak_tflops": 157.3,
+                                 "frac_of_fp32_vector_peak": round(fwd_tops / 157.3, 4),
                                  "hbm": {"achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS,
                                          "unit": "GB/s", "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
                                          "bytes_per_launch": fwd_bytes,
                                          "unit_bytes": "the tape written ((4m + n) FP32 words per frame-iteration) "
                                                        "+ LLRs, syndromes and target bits read"}},
-            "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "judged": judged}
+            "backward_roofline": {"bound": "hbm", "achieved": round(bwd_gbs, 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(bwd_gbs / HBM_PEAK_GBS, 4),
+                                  "bytes_per_launch": bwd_bytes,
+                                  "unit_bytes": "the tape read once + syndromes and target bits read + per-frame "
+                                                "offset gradients written",
+                                  "alu": {"achieved": round(bwd_tops, 3), "peak": FP32_ALU_PEAK_TOPS,
+                                          "unit": "TOP/s", "frac": round(bwd_tops / FP32_ALU_PEAK_TOPS, 4),
+                                          "frac_of_fp32_vector_peak": round(bwd_tops / 157.3, 4),
+                                          "unit_ops": f"10 FP32 ops per edge-iteration x {edge_iters:.0f} "
+                                                      "edge-iterations"}},
+            "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "judged_at_training_rate": judged,
+            "equal_fer": equal_fer,
+            "note": "offsets learned on the FP32 offset min-sum relaxation; rcbp_learned applies the same "
+                    "integer table to the RCBP check node (the paper's decoder has no trainable relaxation)"}
 
 
 def retry_figure(n_frames, extra=2048, step=512, max_rounds=12):
@@ -621,6 +678,221 @@ def large_frames(steps, warmup):
     return out
 
 
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed_launches(gc, d_syn, d_llr, F, max_iter, steps, warmup):
+    """K single-launch decode steps of resident buffers on torch's current stream
+    (the stream the library launches on), with HIP events around every launch
+    and around the whole run. Returns (ms per step, mean launch ms, outputs)."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+
+    n_bytes = (gc.n + 7) // 8
+    d_bits = torch.zeros((F, n_bytes), dtype=torch.uint8, device="cuda")
+    d_conv = torch.zeros(F, dtype=torch.uint8, device="cuda")
+    d_iters = torch.zeros(F, dtype=torch.int32, device="cuda")
+    ws_bytes = B.ldpc_workspace_bytes(gc, F)
+    d_ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda") if ws_bytes else None
+
+    def step():
+        B.ldpc_decode_batch_ex(gc, d_syn, d_llr, F, max_iter, d_bits, d_conv, d_iters, None, None, d_ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for i in range(steps):
+        ev[i][0].record()
+        step()
+        ev[i][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_per_step = t0.elapsed_time(t1) / steps
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    return ms_per_step, kernel_ms, (d_bits.cpu().numpy(), d_conv.cpu().numpy(), d_iters.cpu().numpy())
+
+
+def operating_point(gc, wl, code, n_short, steps, warmup, fer_frames, with_lds=False):
+    """One shortening of the headline workload: the timed 256-frame launches
+    (corrected-key throughput, the roofline of the decode kernel) and the frame
+    error rate on fer_frames fresh frames of the same shortening."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import binding as B
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+
+    fr = I.make_frames(code, wl.frames, wl.qber, 10107, n_short=n_short)
+    F = fr.n_frames
+    d_syn = torch.from_numpy(fr.syn).cuda()
+    d_llr = torch.from_numpy(fr.llr).cuda()
+    ms_per_step, kernel_ms, ref = timed_launches(gc, d_syn, d_llr, F, wl.max_iter, steps, warmup)
+    bits_p, conv, iters = ref
+    correct, undetected = M.frame_outcomes(fr.x, I.unpack_bits(bits_p, code.n), conv)
+    key_ok = float(fr.key_bits()[correct].sum())
+    value = key_ok / (ms_per_step / 1e3) / 1e6
+    fails = int(F - correct.sum())
+    f_eff = float(np.mean(M.efficiency(code.n, code.m, fr.n_punct, fr.n_short, fr.qber)))
+
+    # frame error rate on fresh frames (the timed batch is too small to show 1e-2)
+    big = I.make_frames(code, fer_frames, wl.qber, 20190325, n_short=n_short)
+    got = B.decode(gc, big.syn, big.llr, wl.max_iter)
+    ok_b, und_b = M.frame_outcomes(big.x, I.unpack_bits(got["bits"], code.n), got["conv"])
+    fails_b = int(fer_frames - ok_b.sum())
+
+    family = gc.plan()["kernel"]
+    bytes_per_edge_iter = 6 if wl.acc_bits == 16 else 4
+    edge_iters = float(code.n_edges) * float(iters.sum())
+    io_bytes = F * (code.n + (code.m + 7) // 8 + (code.n + 7) // 8 + 5)
+    alg_bytes = bytes_per_edge_iter * edge_iters + io_bytes
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    degs = [int((code.base[b] >= 0).sum()) for b in range(code.mb)]
+    int_ops = algorithmic_int_ops((code.z, degs), iters.sum())
+    alu_tops = int_ops / (kernel_ms / 1e3) / 1e12
+    traffic = measured_traffic(wl.name) if family == HEADLINE_FAMILY and n_short == int(
+        round(I.WORKLOADS[wl.name].short_frac * code.n)) else None
+    rl = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+          "kernel": KERNEL_SYMBOLS.get(family, family), "family": family, "kernel_ms": round(kernel_ms, 4),
+          "algorithmic_bytes_per_launch": alg_bytes,
+          "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration (L and E each read and written once) x "
+                        f"{edge_iters:.0f} edge-iterations + {io_bytes} B frame I/O",
+          "note": "HBM-equivalent: the decoder state stays in LDS and registers, so the measured HBM traffic "
+                  "(traffic) is the frame I/O; the kernel is bound by integer VALU issue (alu)",
+          "alu": {"achieved": round(alu_tops, 2), "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
+                  "frac": round(alu_tops / ALU_PEAK_TOPS, 4), "algorithmic_ops_per_launch": int_ops,
+                  "unit_ops": "14 int ops per edge-iteration + 27 per (row degree - 2) per check row-iteration; "
+                              f"{int(iters.sum())} frame-iterations of {code.n_edges} edges",
+                  "peak_source": "256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (packed 16-bit)"},
+          # one frame per CU: the launch lasts as long as its slowest frame, so
+          # the CUs of the other frames idle for the rest of it
+          "tail": {"frames": F, "cus": torch.cuda.get_device_properties(0).multi_processor_count,
+                   "mean_iters": round(float(iters.mean()), 3), "max_iters": int(iters.max()),
+                   "cu_busy_frac": round(float(iters.mean()) / max(int(iters.max()), 1), 4)}}
+    if with_lds and family in ("split_reg", "split", "pairs", "lds"):
+        # the decoder state lives on chip: its state traffic against the measured
+        # LDS read peaks (byte reads are the width of the decoder's E accesses)
+        peaks = lds_peaks()
+        lds_bytes = bytes_per_edge_iter * edge_iters
+        lds_achieved = lds_bytes / (kernel_ms / 1e3) / 1e9
+        rl["lds"] = {"achieved": round(lds_achieved, 1), "unit": "GB/s",
+                     "peak_read_u8": peaks["read_u8"], "peak_read_b128": peaks["read_b128"],
+                     "frac_of_u8_peak": round(lds_achieved / peaks["read_u8"], 4),
+                     "frac_of_b128_peak": round(lds_achieved / peaks["read_b128"], 4),
+                     "algorithmic_bytes_per_launch": lds_bytes,
+                     "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration x {edge_iters:.0f} edge-iterations",
+                     "peak_source": "ldpc_probe_lds_bandwidth, measured in this run"}
+    return {"short_frac": round(n_short / code.n, 4), "shortened": n_short, "mbit_s": round(value, 2),
+            "ms_per_step": round(ms_per_step, 4), "frames_per_launch": F,
+            "fer": round(fails_b / fer_frames, 5),
+            "fer_ci95": [round(v, 5) for v in M.wilson_interval(fails_b, fer_frames)],
+            "fer_frames": fer_frames, "undetected_fer_frames": int(und_b.sum()),
+            "fer_batch": round(fails / F, 5), "fer_batch_ci95": [round(v, 5) for v in M.wilson_interval(fails, F)],
+            "undetected_errors": int(undetected.sum()), "efficiency_f": round(f_eff, 4),
+            "mean_iters": round(float(iters.mean()), 3), "max_iters": int(iters.max()),
+            "key_bits_ok": key_ok, "roofline": rl,
+            "_frames": fr, "_syn": d_syn, "_llr": d_llr, "_ref": ref}
+
+
+def float_bp_comparison(gc, wl, code, shorts, n_frames):
+    """FP64 layered BP (the oracle, on the host's cores) beside the integer
+    decoder (the library, on the GPU) on the same frames at each shortening:
+    frame error rates with Wilson intervals, efficiency, mean iterations and the
+    integer-minus-float FER gap. The floating-point decoder reads the unquantized
+    channel LLRs (ln((1-q)/q), shortened positions at a large fixed value)."""
+    import numpy as np
+    import oracle as O
+    from paper_1903_10107_amd import binding as B
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    rows = []
+    for ns in shorts:
+        fr = I.make_frames(code, n_frames, wl.qber, 31415, n_short=ns)
+        t = time.perf_counter()
+        fl = O.bp_fp64_decode(code.base, code.z, fr.syn, fr.llr_f, wl.max_iter, n_threads=threads)
+        el = time.perf_counter() - t
+        it = B.decode(gc, fr.syn, fr.llr, wl.max_iter)
+        ok_f, _ = M.frame_outcomes(fr.x, I.unpack_bits(fl["bits"], code.n), fl["conv"])
+        ok_i, _ = M.frame_outcomes(fr.x, I.unpack_bits(it["bits"], code.n), it["conv"])
+        ff, fi = int(n_frames - ok_f.sum()), int(n_frames - ok_i.sum())
+        rows.append({"short_frac": round(ns / code.n, 4), "shortened": ns, "frames": n_frames,
+                     "efficiency_f": round(float(np.mean(M.efficiency(code.n, code.m, fr.n_punct, fr.n_short,
+                                                                      fr.qber))), 4),
+                     "fer_fp64_bp": round(ff / n_frames, 5),
+                     "fer_fp64_bp_ci95": [round(v, 5) for v in M.wilson_interval(ff, n_frames)],
+                     "fer_int8": round(fi / n_frames, 5),
+                     "fer_int8_ci95": [round(v, 5) for v in M.wilson_interval(fi, n_frames)],
+                     "fer_gap_int8_minus_fp64": round((fi - ff) / n_frames, 5),
+                     "mean_iters_fp64_bp": round(float(fl["iters"].mean()), 3),
+                     "mean_iters_int8": round(float(it["iters"].mean()), 3),
+                     "fp64_seconds": round(el, 2)})
+        print(f"[float-bp] {wl.name} shortened {ns}: fp64 FER {ff}/{n_frames}, int8 FER {fi}/{n_frames}, "
+              f"{el:.1f} s", file=sys.stderr, flush=True)
+    return {"kind": "oracle", "decoder": "FP64 layered BP, exact box-plus (Eq. 6), same schedule and stopping rule",
+            "cores": threads, "points": rows}
+
+
+def float_compare(args):
+    """The FP64-BP-versus-integer table of the profiles: the headline code at its
+    two operating points and each bucket of the ragged rate-adaptive batch."""
+    import numpy as np
+    import oracle as O
+    import torch
+    from paper_1903_10107_amd import binding as B
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+
+    torch.cuda.set_device(0)
+    wl = I.WORKLOADS["n32768_q2"]
+    code = wl.code()
+    gc = B.Code(code.base, code.z)
+    shorts = [int(round(wl.short_frac * code.n))] + ([args.least_short] if args.least_short is not None else [])
+    res = {"headline": float_bp_comparison(gc, wl, code, shorts, args.float_frames)}
+    print(json.dumps(res), flush=True)
+    rcode = I.Code(I.make_base(24, 48, 2048), 2048)
+    rgc = B.Code(rcode.base, rcode.z)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    buckets = []
+    for q in I.RAGGED_QBERS:
+        p, sh = I.RAGGED_POINTS[q]
+        fr = I.make_frames(rcode, args.ragged_float_frames, q, 27182, n_punct=p, n_short=sh)
+        t = time.perf_counter()
+        fl = O.bp_fp64_decode(rcode.base, rcode.z, fr.syn, fr.llr_f, 60, n_threads=threads)
+        el = time.perf_counter() - t
+        it = B.decode(rgc, fr.syn, fr.llr, 60)
+        ok_f, _ = M.frame_outcomes(fr.x, I.unpack_bits(fl["bits"], rcode.n), fl["conv"])
+        ok_i, _ = M.frame_outcomes(fr.x, I.unpack_bits(it["bits"], rcode.n), it["conv"])
+        n = fr.n_frames
+        ff, fi = int(n - ok_f.sum()), int(n - ok_i.sum())
+        row = {"qber": q, "punctured": p, "shortened": sh, "frames": n,
+               "efficiency_f": round(float(M.efficiency(rcode.n, rcode.m, p, sh, q)), 4),
+               "fer_fp64_bp": round(ff / n, 5), "fer_fp64_bp_ci95": [round(v, 5) for v in M.wilson_interval(ff, n)],
+               "fer_int8": round(fi / n, 5), "fer_int8_ci95": [round(v, 5) for v in M.wilson_interval(fi, n)],
+               "fer_gap_int8_minus_fp64": round((fi - ff) / n, 5),
+               "mean_iters_fp64_bp": round(float(fl["iters"].mean()), 3),
+               "mean_iters_int8": round(float(it["iters"].mean()), 3), "fp64_seconds": round(el, 1)}
+        buckets.append(row)
+        print(json.dumps({"ragged_bucket": row}), flush=True)
+    res["ragged"] = {"code": "24x48 QC base, Z=2048 (n=98304, R=1/2), 60 iterations", "buckets": buckets}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -630,6 +902,19 @@ def main():
     ap.add_argument("--short-frac", type=float, default=None,
                     help="override the workload's shortened fraction (operating-point studies)")
     ap.add_argument("--frames", type=int, default=None, help="override the workload's batch size")
+    ap.add_argument("--least-short", type=int, default=I_LEAST_SHORT,
+                    help="shortened positions of the least-shortening FER <= 1e-2 point, measured beside "
+                         "the value point (negative: skip)")
+    ap.add_argument("--fer-frames", type=int, default=4096,
+                    help="fresh frames decoded at each operating point for its frame error rate")
+    ap.add_argument("--float-frames", type=int, default=512,
+                    help="frames per operating point decoded by the FP64 BP oracle beside the integer "
+                         "decoder in the CPU-baseline leg (0: skip)")
+    ap.add_argument("--ragged-float-frames", type=int, default=1024,
+                    help="frames per ragged bucket in --float-compare")
+    ap.add_argument("--float-compare", action="store_true",
+                    help="print the FP64-BP-versus-integer table (headline operating points and the "
+                         "ragged buckets) and exit")
     ap.add_argument("--batched-frames", type=int, default=4096,
                     help="frames of the same workload decoded per launch for the batched figure (0: skip)")
     ap.add_argument("--ragged-frames", type=int, default=2048,
@@ -656,6 +941,8 @@ def main():
                     help="instead of decoding, run a plain device copy of BYTES bytes per step "
                          "(reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    if args.least_short is not None and args.least_short < 0:
+        args.least_short = None
     if args.gpus != 1:
         print(f"bench.py measures one GPU: frames are independent, so N GPUs would each decode their own "
               f"batch with no exchange; --gpus {args.gpus} is not run.", file=sys.stderr)
@@ -669,6 +956,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, args.steps, args.warmup)
+        return
+    if args.float_compare:
+        float_compare(args)
         return
     if args.only:
         torch.cuda.set_device(0)
@@ -701,119 +991,63 @@ def main():
                   [float(v) for v in args.qber_sweep.split(",")] if args.qber_sweep else None)
         return
     n_short = int(round(wl.short_frac * code.n))
-    fr = I.make_frames(code, wl.frames, wl.qber, 10107, n_short=n_short)
     torch.cuda.set_device(0)
     gc = B.Code(code.base, code.z, acc_bits=wl.acc_bits)
-    F = fr.n_frames
-    dev = "cuda"
-    d_syn = torch.from_numpy(fr.syn).to(dev)
-    d_llr = torch.from_numpy(fr.llr).to(dev)
-    d_bits = torch.zeros((F, (code.n + 7) // 8), dtype=torch.uint8, device=dev)
-    d_conv = torch.zeros(F, dtype=torch.uint8, device=dev)
-    d_iters = torch.zeros(F, dtype=torch.int32, device=dev)
-    ws_bytes = B.ldpc_workspace_bytes(gc, F)
-    d_ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev) if ws_bytes else None
-
-    def step():
-        B.ldpc_decode_batch_ex(gc, d_syn, d_llr, F, wl.max_iter, d_bits, d_conv, d_iters, None, None, d_ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    K = args.steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for i in range(K):
-        ev[i][0].record()
-        step()
-        ev[i][1].record()
-    t1.record()
-    torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    ms_per_step = total_ms / K
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-
-    bits = I.unpack_bits(d_bits.cpu().numpy(), code.n)
-    conv = d_conv.cpu().numpy()
-    iters = d_iters.cpu().numpy()
-    correct, undetected = M.frame_outcomes(fr.x, bits, conv)
-    key_bits = fr.key_bits()
-    value = float(key_bits[correct].sum()) / (ms_per_step / 1e3) / 1e6
-    fails = int(F - correct.sum())
-    f_eff = float(np.mean(M.efficiency(code.n, code.m, fr.n_punct, fr.n_short, fr.qber)))
-
-    bytes_per_edge_iter = 6 if wl.acc_bits == 16 else 4
-    edge_iters = float(code.n_edges) * float(iters.sum())
-    io_bytes = F * (code.n + (code.m + 7) // 8 + (code.n + 7) // 8 + 5)
-    alg_bytes = bytes_per_edge_iter * edge_iters + io_bytes
-    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload)
-    degs = [int((code.base[b] >= 0).sum()) for b in range(code.mb)]
-    int_ops = algorithmic_int_ops((code.z, degs), iters.sum())
-    alu_tops = int_ops / (kernel_ms / 1e3) / 1e12
-
+    fer_frames = max(args.fer_frames, wl.frames)
+    point = operating_point(gc, wl, code, n_short, args.steps, args.warmup, fer_frames, with_lds=True)
+    fr, d_syn, d_llr, ref = point.pop("_frames"), point.pop("_syn"), point.pop("_llr"), point.pop("_ref")
+    rl = point["roofline"]
     out = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": point["mbit_s"],
         "unit": "Mbit/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": point["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int16" if wl.acc_bits == 16 else "int8",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": code.n, "frames": F, "qber": wl.qber, "shortened": n_short,
+        "config": {"workload": wl.name, "n": code.n, "frames": wl.frames, "qber": wl.qber, "shortened": n_short,
                    "short_frac": wl.short_frac,
                    "max_iter": wl.max_iter, "code": f"{wl.mb}x{wl.nb} QC base, Z={wl.z}, column weight 3",
-                   "decoder": "plain (RCBP forward-backward check node, saturating VN)"},
-        "roofline": {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(ALU_PEAK_TOPS, 1),
-                     "unit": "TOP/s", "frac": round(alu_tops / ALU_PEAK_TOPS, 4), "traffic": traffic,
-                     "kernel": f"k_decode_frame ({gc.plan()['kernel']} variant)", "kernel_ms": round(kernel_ms, 4),
-                     "algorithmic_ops_per_launch": int_ops,
-                     "unit_ops": "14 int ops per edge-iteration + 27 per (row degree - 2) per check row-iteration; "
-                                 f"{iters.sum()} frame-iterations of {code.n_edges} edges",
-                     "hbm_equivalent": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                        "frac": round(achieved / HBM_PEAK_GBS, 4),
-                                        "algorithmic_bytes_per_launch": alg_bytes,
-                                        "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration x "
-                                                      f"{edge_iters:.0f} edge-iterations + {io_bytes} B frame I/O"},
-                     # one frame per CU: the launch lasts as long as its slowest frame, so
-                     # the CUs of the other frames idle for the rest of it
-                     "tail": {"frames": F, "cus": torch.cuda.get_device_properties(0).multi_processor_count,
-                              "mean_iters": round(float(iters.mean()), 3), "max_iters": int(iters.max()),
-                              "cu_busy_frac": round(float(iters.mean()) / max(int(iters.max()), 1), 4)}},
-        "fer": round(fails / F, 5),
-        "fer_ci95": [round(v, 5) for v in M.wilson_interval(fails, F)],
-        "undetected_errors": int(undetected.sum()),
-        "efficiency_f": round(f_eff, 4),
-        "mean_iters": round(float(iters.mean()), 3),
-        "max_iters_in_batch": int(iters.max()),
+                   "decoder": "plain (RCBP forward-backward check node, saturating VN)",
+                   "operating_point": "the value point of the single-launch form (design notes, measurement); "
+                                      "the least-shortening point with FER <= 1e-2 is in operating_points"},
+        "roofline": rl,
+        "fer": point["fer_batch"],
+        "fer_ci95": point["fer_batch_ci95"],
+        "undetected_errors": point["undetected_errors"],
+        "efficiency_f": point["efficiency_f"],
+        "mean_iters": point["mean_iters"],
+        "max_iters_in_batch": point["max_iters"],
         "paper_context": "57.6 Mbit/s at f=1.108 on a 4-core i7-6700HQ with its own irregular codes (context only)",
     }
-    if gc.plan()["kernel"] in ("split", "pairs", "lds"):
-        # the decoder state lives in LDS: its state traffic against the measured
-        # LDS read peaks (byte reads are the width of the decoder's accesses)
-        peaks = lds_peaks()
-        lds_bytes = bytes_per_edge_iter * edge_iters
-        lds_achieved = lds_bytes / (kernel_ms / 1e3) / 1e9
-        out["roofline"]["lds"] = {"achieved": round(lds_achieved, 1), "unit": "GB/s",
-                                  "peak_read_u8": peaks["read_u8"], "peak_read_b128": peaks["read_b128"],
-                                  "frac_of_u8_peak": round(lds_achieved / peaks["read_u8"], 4),
-                                  "frac_of_b128_peak": round(lds_achieved / peaks["read_b128"], 4),
-                                  "algorithmic_bytes_per_launch": lds_bytes,
-                                  "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration (E and L read and "
-                                                f"written once) x {edge_iters:.0f} edge-iterations",
-                                  "peak_source": "ldpc_probe_lds_bandwidth, measured in this run"}
-    out["end_to_end"] = end_to_end(gc, code, fr, wl.max_iter, float(key_bits[correct].sum()),
+    pts = {"value_point": {k: v for k, v in point.items() if k != "roofline"}}
+    pts["value_point"]["hbm_equivalent_frac"] = rl["frac"]
+    pts["value_point"]["alu_frac"] = rl["alu"]["frac"]
+    if args.least_short is not None and args.least_short != n_short:
+        lp = operating_point(gc, wl, code, args.least_short, args.steps, args.warmup, fer_frames, with_lds=False)
+        lfr, l_syn, l_llr, lref = lp.pop("_frames"), lp.pop("_syn"), lp.pop("_llr"), lp.pop("_ref")
+        lrl = lp.pop("roofline")
+        lp["hbm_equivalent_frac"] = lrl["frac"]
+        lp["alu_frac"] = lrl["alu"]["frac"]
+        lp["tail"] = lrl["tail"]
+        lp["kernel_ms"] = lrl["kernel_ms"]
+        if args.pipelined_streams > 1:
+            lp["pipelined"] = pipelined(gc, code, lfr, l_syn, l_llr, wl.max_iter, lref, args.steps, args.warmup,
+                                        args.pipelined_streams)
+        lp["origin"] = ("least shortening with FER <= 1e-2 at QBER 2%: bisection over the shortened "
+                        "positions (paper_1903_10107_amd.rate, 2048 frames per probe, 256-position steps)")
+        pts["least_shortening"] = lp
+        del lfr, l_syn, l_llr
+    out["operating_points"] = pts
+    out["end_to_end"] = end_to_end(gc, code, fr, wl.max_iter, point["key_bits_ok"],
                                    max(10, args.steps // 5), max(1, args.warmup))
     if args.pipelined_streams > 1:
-        out["pipelined"] = pipelined(gc, code, fr, d_syn, d_llr, wl.max_iter,
-                                     (d_bits.cpu().numpy(), conv, iters), args.steps, args.warmup,
+        out["pipelined"] = pipelined(gc, code, fr, d_syn, d_llr, wl.max_iter, ref, args.steps, args.warmup,
                                      args.pipelined_streams)
     if args.batched_frames:
         out["batched"] = batched(wl, code, n_short, args.batched_frames, args.steps, args.warmup)
@@ -831,6 +1065,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
         if not args.no_large:
             out["cpu_baseline"]["large"] = cpu_baseline_large(args.cpu_seconds / 3)
+        if args.float_frames:
+            shorts = [n_short] + ([args.least_short] if args.least_short is not None else [])
+            out["cpu_baseline"]["float_bp"] = float_bp_comparison(gc, wl, code, shorts, args.float_frames)
     print(json.dumps(out), flush=True)
 
 
