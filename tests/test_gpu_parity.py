@@ -238,7 +238,32 @@ def test_parity_full_n32768_sampled(B):
 
 
 def test_parity_full_n1048576_sampled(B):
-    _full_size(B, "n1048576_q2", sample=np.array([0, 31]))
+    _full_size(B, "n1048576_q2", sample=np.array([0, 9, 22, 31]))
+
+
+def test_parity_n1048576_shortened_early_stop(B):
+    """The shortened n = 2^20 decode as the benchmark runs it: 16-bit soft values,
+    the layer-synchronous family, the host stopping the launches once every frame
+    has retired (check_every = 1); every frame against the oracle."""
+    import torch
+    wl = I.WORKLOADS["n1048576_q2"]
+    code = wl.code()
+    F = 6
+    fr = I.make_frames(code, F, wl.qber, 10107, n_short=int(0.33 * code.n))
+    gc = B.Code(code.base, code.z, acc_bits=wl.acc_bits)
+    assert gc.plan()["kernel"] == "layer_sync"
+    _say(f"[gpu parity] n1048576 shortened, check_every=1, F={F}")
+    syn, llr = torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda()
+    bits = torch.zeros((F, (code.n + 7) // 8), dtype=torch.uint8, device="cuda")
+    conv = torch.zeros(F, dtype=torch.uint8, device="cuda")
+    iters = torch.full((F,), -1, dtype=torch.int32, device="cuda")
+    B.ldpc_decode_batch_sched(gc, syn, llr, F, wl.max_iter, bits, conv, iters, check_every=1)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, wl.max_iter, acc_bits=wl.acc_bits)
+    assert ref["conv"].all() and ref["iters"].max() < wl.max_iter
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+    assert np.array_equal(conv.cpu().numpy(), ref["conv"])
+    assert np.array_equal(iters.cpu().numpy(), ref["iters"])
 
 
 @pytest.mark.parametrize("kernel", ["split_reg", "split", "pairs", "global", "layer_sync"])
