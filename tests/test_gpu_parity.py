@@ -184,10 +184,12 @@ def test_binding_rejects_short_buffers(B):
 
 
 @pytest.mark.parametrize("mb,nb,z,frames,misalign", [
-    (5, 32, 32, 5, 0),       # word kernel (Z a multiple of 32), one partial workgroup
+    (5, 32, 32, 5, 0),       # word kernel (Z a multiple of 32, fewer than 8 frames), one partial workgroup
     (4, 12, 37, 5, 0),       # Z not a multiple of 32: bit kernel
     (5, 32, 1024, 5, 0),     # word kernel, the n = 32768 code
     (5, 32, 1024, 300, 0),   # word kernel, many frames (workgroups span frames)
+    (10, 64, 16384, 11, 0),  # word kernel grouped by XCD (the n = 2^20 code), frames not a multiple of 8
+    (4, 32, 16384, 8, 0),    # grouped by XCD, exactly 8 workgroups per frame
     (3, 8, 96, 130, 0),      # Z = 3 x 32, not a power of two: 3 words per block
     (5, 32, 1024, 130, 1),   # buffers not 4-byte aligned: bit kernel with the frame in LDS
     (5, 32, 1024, 5, 1),     # the same with few frames: row-parallel bit kernel
