@@ -249,6 +249,46 @@ def batched(wl, code, n_short, n_frames, steps, warmup):
             "undetected_errors": int(undetected.sum()), "mean_iters": round(float(iters.mean()), 3)}
 
 
+def small_frames(batches, steps, warmup):
+    """Short frames: the n = 1024 workload (5x32 base, Z = 32, QBER 1%, 50
+    iterations), 64 frames as configured and larger batches for throughput,
+    under the autotuner with the frames-per-workgroup axis (a frame is 32 lanes:
+    two frames per wave, 1 to 16 waves per workgroup, no workgroup barrier)
+    against one frame per 64-thread workgroup."""
+    import numpy as np
+    import torch
+    from paper_1903_10107_amd import inputs as I
+    from paper_1903_10107_amd import metrics as M
+    from paper_1903_10107_amd import tune
+
+    wl = I.WORKLOADS["n1024_q1"]
+    code = wl.code()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"workload": wl.name, "code": "5x32 QC base, Z=32, column weight 3 (n=1024)", "qber": wl.qber,
+           "max_iter": wl.max_iter}
+    for F in batches:
+        fr = I.make_frames(code, F, wl.qber, 10107)
+        cands = [tune.Schedule("split_reg", 0, "none", False), tune.Schedule("split_reg", 0, "none", True)]
+        cands += [c for c in tune.candidates(n_cu, False, code.z) if c.frames_per_workgroup]
+        cands += [tune.Schedule("split_reg", 0, "none", True, 0, 2 * w) for w in (4, 16)]
+        best = tune.tune(code.base, code.z, fr.syn, fr.llr, wl.max_iter, cache_path=None, cands=cands, reps=3)
+        run = tune.Runner(code.base, code.z, fr.syn, fr.llr, wl.max_iter, tune.Schedule(**best["schedule"]))
+        ms = tune.time_ms(run, max(5, steps // 5), max(1, warmup))
+        bits, conv, iters = run.outputs()
+        ok, und = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
+        alg = 4 * float(code.n_edges) * float(iters.sum()) + F * (code.n + (code.m + 7) // 8 + (code.n + 7) // 8 + 5)
+        fails = int(F - ok.sum())
+        out[f"frames_{F}"] = {"frames": F, "ms_per_launch": round(ms, 4),
+                              "mbit_s": round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2),
+                              "hbm_equivalent_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "fer": round(fails / F, 5),
+                              "fer_ci95": [round(v, 5) for v in M.wilson_interval(fails, F)],
+                              "undetected_errors": int(und.sum()), "mean_iters": round(float(iters.mean()), 3),
+                              "max_iters": int(iters.max()), "schedule": best["schedule"],
+                              "schedules_tried": best["candidates"]}
+    return out
+
+
 def batched_headline(n_frames, steps, warmup):
     """The batched figure on the headline workload (for profiling it alone)."""
     from paper_1903_10107_amd import inputs as I
@@ -946,6 +986,8 @@ def main():
     ap.add_argument("--retry-frames", type=int, default=2048,
                     help="frames of the reveal-and-retry figure on the ragged batch (0: skip)")
     ap.add_argument("--no-large", action="store_true", help="skip the n = 1048576 figure")
+    ap.add_argument("--small-frames", default="64,65536",
+                    help="batch sizes of the n = 1024 short-frame figure (empty: skip)")
     ap.add_argument("--syndrome-frames", type=int, default=4096,
                     help="frames of the syndrome-encoder figure (Alice's side; 0: skip)")
     ap.add_argument("--pipelined-streams", type=int, default=3,
@@ -957,7 +999,8 @@ def main():
     ap.add_argument("--qber-sweep", default="",
                     help="comma-separated QBERs for --fer-sweep (default: the workload's)")
     ap.add_argument("--sweep-frames", type=int, default=4096)
-    ap.add_argument("--only", choices=("learned", "syndrome", "retry", "large", "batched", "ragged"), default=None,
+    ap.add_argument("--only", choices=("learned", "syndrome", "retry", "large", "batched", "ragged", "small"),
+                    default=None,
                     help="run one figure alone and print it as one JSON line (for profiling its kernels)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="instead of decoding, run a plain device copy of BYTES bytes per step "
@@ -989,7 +1032,9 @@ def main():
                "retry": lambda: retry_figure(args.retry_frames),
                "large": lambda: large_frames(args.steps, args.warmup),
                "batched": lambda: batched_headline(args.batched_frames, args.steps, args.warmup),
-               "ragged": lambda: ragged(args.ragged_frames, args.steps, args.warmup)}[args.only]()
+               "ragged": lambda: ragged(args.ragged_frames, args.steps, args.warmup),
+               "small": lambda: small_frames([int(v) for v in args.small_frames.split(",") if v],
+                                             args.steps, args.warmup)}[args.only]()
         print(json.dumps({"figure": args.only, args.only: fig}), flush=True)
         return
     if args.workload == "n98304_ragged":
@@ -1083,6 +1128,8 @@ def main():
         out["syndrome"] = syndrome_figure(args.syndrome_frames, args.steps, args.warmup)
     if not args.no_large:
         out["large"] = large_frames(args.steps, args.warmup)
+    if args.small_frames:
+        out["small"] = small_frames([int(v) for v in args.small_frames.split(",") if v], args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
         if not args.no_large:

@@ -196,6 +196,13 @@ typedef struct {
                                       launches no further iterations. The call (or
                                       ldpc_batch_launch) then returns only when the decode
                                       has finished; results are the same. */
+    int32_t frames_per_workgroup;  /* 0: one frame per workgroup. > 0: that many frames per
+                                      workgroup, each frame's z lanes inside one wave (64 / z
+                                      frames per wave, no workgroup barrier); needs the
+                                      LDPC_KERNEL_SPLIT_REG family with z <= 64, a multiple of
+                                      64 / z, at most 16 waves per workgroup, all frames' soft
+                                      values within 64 KB of LDS, and no persistent schedule
+                                      (LDPC_EUNSUPPORTED / LDPC_EINVAL otherwise). */
 } ldpc_schedule;
 
 /* ldpc_decode_batch_ex with a schedule (NULL = default). The decoded results do

@@ -48,7 +48,8 @@ class ldpc_params(C.Structure):
 
 
 class ldpc_schedule(C.Structure):
-    _fields_ = [("persistent_workgroups", C.c_int32), ("order", C.c_void_p), ("check_every", C.c_int32)]
+    _fields_ = [("persistent_workgroups", C.c_int32), ("order", C.c_void_p), ("check_every", C.c_int32),
+                ("frames_per_workgroup", C.c_int32)]
 
 
 _lib = None
@@ -275,10 +276,11 @@ def ldpc_decode_batch(code: Code, syndromes, llr_in, n_frames: int, max_iter: in
     _check(lib().ldpc_decode_batch(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, _stream_ptr(stream)))
 
 
-def _schedule(n_frames: int, persistent_workgroups: int, order, check_every: int = 0):
+def _schedule(n_frames: int, persistent_workgroups: int, order, check_every: int = 0,
+              frames_per_workgroup: int = 0):
     import torch
     p_order = _dev_ptr(order, torch.int32, (n_frames,), "order")
-    return ldpc_schedule(int(persistent_workgroups), p_order, int(check_every))
+    return ldpc_schedule(int(persistent_workgroups), p_order, int(check_every), int(frames_per_workgroup))
 
 
 def ldpc_workspace_bytes_sched(code: Code, n_frames: int, persistent_workgroups: int = 0) -> int:
@@ -288,7 +290,7 @@ def ldpc_workspace_bytes_sched(code: Code, n_frames: int, persistent_workgroups:
 
 def ldpc_decode_batch_sched(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
                             out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, stream=None,
-                            check_every: int = 0):
+                            check_every: int = 0, frames_per_workgroup: int = 0):
     import torch
     F = int(n_frames)
     if F < 0:
@@ -301,7 +303,7 @@ def ldpc_decode_batch_sched(code: Code, syndromes, llr_in, n_frames: int, max_it
     p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
     p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
     p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
-    sch = _schedule(F, persistent_workgroups, order, check_every)
+    sch = _schedule(F, persistent_workgroups, order, check_every, frames_per_workgroup)
     need = int(lib().ldpc_workspace_bytes_sched(code.handle, F, C.byref(sch)))
     p_ws, ws_bytes = None, 0
     if workspace is not None:
@@ -316,7 +318,7 @@ STATIC_WORKSPACE_BYTES = 64 << 20   # LDPC_STATIC_WORKSPACE_BYTES
 
 def ldpc_decode_batch_static(code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
                              out_iters=None, persistent_workgroups: int = 0, order=None, stream=None,
-                             check_every: int = 0):
+                             check_every: int = 0, frames_per_workgroup: int = 0):
     """ldpc_decode_batch_sched with the library's static workspace (no device
     allocation by the library or here)."""
     import torch
@@ -331,7 +333,7 @@ def ldpc_decode_batch_static(code: Code, syndromes, llr_in, n_frames: int, max_i
     p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
     p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
     p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
-    sch = _schedule(F, persistent_workgroups, order, check_every)
+    sch = _schedule(F, persistent_workgroups, order, check_every, frames_per_workgroup)
     _check(lib().ldpc_decode_batch_static(code.handle, p_syn, p_llr, F, int(max_iter), p_bits, p_conv, p_it,
                                           C.byref(sch), _stream_ptr(stream)))
 
@@ -340,7 +342,8 @@ class Batch:
     """A decode of fixed device buffers captured as a HIP graph (ldpc_batch_*)."""
 
     def __init__(self, code: Code, syndromes, llr_in, n_frames: int, max_iter: int, out_bits, out_converged,
-                 out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, check_every: int = 0):
+                 out_iters=None, persistent_workgroups: int = 0, order=None, workspace=None, check_every: int = 0,
+                 frames_per_workgroup: int = 0):
         import torch
         self._h = None
         F = int(n_frames)
@@ -351,7 +354,7 @@ class Batch:
         p_bits = _dev_ptr(out_bits, torch.uint8, (F, bb), "out_bits")
         p_conv = _dev_ptr(out_converged, torch.uint8, (F,), "out_converged")
         p_it = _dev_ptr(out_iters, torch.int32, (F,), "out_iters")
-        sch = _schedule(F, persistent_workgroups, order, check_every)
+        sch = _schedule(F, persistent_workgroups, order, check_every, frames_per_workgroup)
         need = int(lib().ldpc_workspace_bytes_sched(code.handle, F, C.byref(sch)))
         p_ws, ws_bytes = None, 0
         if workspace is not None:

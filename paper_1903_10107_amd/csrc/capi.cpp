@@ -299,6 +299,28 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
             return fail(LDPC_EUNSUPPORTED, "ldpc_schedule: persistent workgroups need the split kernel family");
         if (sched->check_every < 0)
             return fail(LDPC_EINVAL, "ldpc_schedule: check_every < 0");
+        const int fpw = sched->frames_per_workgroup;
+        if (fpw < 0)
+            return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup < 0");
+        if (fpw > 0) {
+            const int z = code->h.z;
+            if (!code->plan.split_reg || z > 64)
+                return fail(LDPC_EUNSUPPORTED,
+                            "ldpc_schedule: frames_per_workgroup needs the split_reg family with z <= 64");
+            const int fw = 64 / z;
+            if (fpw % fw != 0 || fpw / fw > 16)
+                return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup must be a multiple of 64 / z, "
+                                         "at most 16 waves");
+            if (sched->persistent_workgroups > 0)
+                return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup and persistent workgroups exclude "
+                                         "each other");
+            const size_t esz = ((size_t)code->h.n + z + 15) & ~(size_t)15;
+            if ((size_t)fpw * esz > 65536)
+                return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup frames' soft values exceed 64 KB");
+            const size_t lds = qkdldpc::wave_reg_lds_bytes(code->h.n, z, (code->h.m + 7) / 8, fpw);
+            if (lds > (size_t)code->lds_limit)
+                return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup needs more LDS than a workgroup has");
+        }
     }
     return LDPC_OK;
 }
@@ -318,6 +340,7 @@ DecodeArgs make_args(const ldpc_code *code, const uint8_t *syndromes, const int8
     A.out_iters = out_iters;
     A.out_L = out_L;
     A.out_E = out_E;
+    A.frames_per_wg = sched ? sched->frames_per_workgroup : 0;
     if (is_persistent(sched)) {
         A.persistent_wgs = sched->persistent_workgroups;
         A.queue = reinterpret_cast<int *>(w);

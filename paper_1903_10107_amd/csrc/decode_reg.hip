@@ -370,9 +370,228 @@ __global__ __launch_bounds__(1024) void k_decode_reg_persistent(DevCode C, Decod
     }
 }
 
+// ---------------------------------------------------------------------------
+// Several frames per workgroup for lifts of at most 64 (frames_per_workgroup in
+// the schedule): a frame's Z lanes (two per row pair) lie in one wave, so a wave
+// decodes 64 / Z frames on its own and a workgroup of W waves decodes
+// W x 64 / Z frames with no workgroup barrier at all. Within a wave the LDS
+// instructions execute in program order, so a layer's E reads follow the
+// previous layer's E writes without a barrier; the syndrome tests are wave
+// ballots over each frame's lanes. Frames of one wave run in lockstep: a frame
+// that has converged stops updating its state (its lanes are masked off) while
+// the other frames of the wave go on.
+// ---------------------------------------------------------------------------
+
+// LDS of the wave kernel: frame slot k's E (plus dummy column) at k * esz, its
+// syndrome at syn_off + k * syn_bytes, then the per-lane address table.
+struct WaveGeom {
+    int fpw;        // frames per workgroup
+    int esz;        // bytes per frame slot's E region (n + Z rounded up to 16)
+    int syn_off;    // LDS offset of the syndromes
+    int tab_off;    // LDS offset of the address table
+};
+
+__host__ __device__ inline WaveGeom wave_geom(int n, int z, int syn_bytes, int fpw, int threads, int mb, int dh)
+{
+    WaveGeom g;
+    g.fpw = fpw;
+    g.esz = (n + z + 15) & ~15;
+    g.syn_off = fpw * g.esz;
+    g.tab_off = (g.syn_off + fpw * syn_bytes + 15) & ~15;
+    (void)threads;
+    (void)mb;
+    (void)dh;
+    return g;
+}
+
+__host__ __device__ inline size_t wave_lds_bytes(int n, int z, int syn_bytes, int fpw, int threads, int mb, int dh)
+{
+    const WaveGeom g = wave_geom(n, z, syn_bytes, fpw, threads, mb, dh);
+    return (size_t)g.tab_off + (size_t)threads * mb * dh * 2;
+}
+
+template <int DMIN, int DMAX, int MB, int RULE>
+__global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs A)
+{
+    constexpr int DH = DMAX / 2;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int z = C.z, n = C.n, hz = z >> 1;
+    const unsigned hzb = (unsigned)hz, zm = (unsigned)(z - 1);
+    const WaveGeom W = wave_geom(n, z, A.syn_bytes, A.frames_per_wg, blockDim.x, MB, DH);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fw = 64 / z;                       // frames per wave
+    const int sub = lane / z;                    // frame of this lane within the wave
+    const int slot = wave * fw + sub;            // frame slot within the workgroup
+    const int lane0 = sub * z;                   // first lane of the frame in the wave
+    const int f = blockIdx.x * W.fpw + slot;
+    const bool valid = f < A.n_frames;
+    const unsigned long long fmask = z == 64 ? ~0ull : ((1ull << z) - 1ull);
+    int8_t *E = reinterpret_cast<int8_t *>(smem) + slot * W.esz;
+    uint8_t *syn_s = smem + W.syn_off + slot * A.syn_bytes;
+
+    RegLds M;
+    M.E = E;
+    M.syn = syn_s;
+    M.addr = reinterpret_cast<uint16_t *>(smem + W.tab_off);
+    M.flags = nullptr;
+    RegLane G;
+    G.tid = tid;
+    G.nthr = blockDim.x;
+    G.h = tid & 1;
+    G.r = (lane - lane0) >> 1;
+    G.active = valid;
+    G.real = 0;
+    {
+        const unsigned ebase = (unsigned)(slot * W.esz), dummy = ebase + (unsigned)(C.nb * z);
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+#pragma unroll
+            for (int i = 0; i < DH; ++i) {
+                const int4 te = A.lane_tab[(b * DH + i) * 2 + G.h];
+                const unsigned a0 =
+                    valid ? ebase + ((((unsigned)G.r + (unsigned)te.x) & zm) | (unsigned)te.y) : dummy;
+                M.addr[tid * (MB * DH) + b * DH + i] = (uint16_t)a0;
+                if (valid && te.z != 0)
+                    G.real |= 1ull << (b * DH + i);
+            }
+    }
+    // 1 when some lane of this lane's frame has pred (a wave ballot)
+    auto frame_any = [&](bool pred) -> bool { return ((__ballot(pred) >> lane0) & fmask) != 0; };
+
+    // stage in, by the frame's own lanes
+    const int lf = lane - lane0;
+    if (valid) {
+        const uint8_t *sg = A.syn + (size_t)f * A.syn_bytes;
+        for (int i = lf; i < A.syn_bytes; i += z)
+            syn_s[i] = sg[i];
+        stage_llr<int8_t>(E, A.llr + (size_t)f * n, n, C.e_max < 127 ? C.e_max : 127, lf, z);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    unsigned synm = 0;
+    if (valid)
+#pragma unroll 1
+        for (int b = 0; b < MB; ++b) {
+            const int i0 = b * z + G.r, i1 = i0 + hz;
+            synm |= (unsigned)((syn_s[i0 >> 3] >> (i0 & 7)) & 1) << b |
+                    (unsigned)((syn_s[i1 >> 3] >> (i1 & 7)) & 1) << (16 + b);
+        }
+
+    const bool u0 = frame_any(reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 0, 1));
+    const bool u1 = frame_any(reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 1, MB));
+    bool conv = valid && !u0 && !u1;
+    bool done = conv || !valid;
+    int iters = 0;
+
+    s16x2 Lr[MB][DH];
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int i = 0; i < DH; ++i)
+            Lr[b][i] = splat2(0);
+
+    for (int t = 1; t <= A.max_iter; ++t) {
+        if (__ballot(!done) == 0)
+            break;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            unsigned a0[DH];
+            reg_addr<MB, DH>(M, G, b, a0);
+            s16x2 e[DH];
+            reg_fetch<DH>(M, a0, hzb, e);
+            if (b == 0 && t >= 2) {
+                // the state after iteration t-1: layer 0 from the values just read,
+                // the other layers only for frames whose layer 0 holds
+                const s16x2 own = reg_parity<DMIN, DMAX>(G, 0, e);
+                const s16x2 pe = reg_syn(synm, 0) ^ own ^ swap_pair(own);
+                const bool pass0 = !frame_any(valid && (pe.x | pe.y) < 0);
+                const bool need = !done && pass0;
+                if (__ballot(need) != 0) {
+                    const bool rest = frame_any(reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 1, MB));
+                    if (need && !rest) {
+                        done = true;
+                        conv = true;
+                        iters = t - 1;
+                    }
+                }
+            }
+            if (!done)
+                reg_finish<DMIN, DMAX, RULE>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb);
+            // the next layer's reads come after these writes in program order
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (!done)
+            iters = t;
+    }
+    {
+        // frames that ran out of iterations: the test after the last one
+        const bool a = frame_any(reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 0, 1));
+        const bool c = frame_any(reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 1, MB));
+        if (valid && !conv && A.max_iter > 0)
+            conv = !a && !c;
+    }
+    if (!conv)
+        iters = A.max_iter;
+
+    // stage out: every frame of the wave in turn, 64 hard decisions per ballot
+    const int nwords = (n + 63) >> 6;
+    for (int k = 0; k < fw; ++k) {
+        const int fk = blockIdx.x * W.fpw + wave * fw + k;
+        if (fk >= A.n_frames)
+            break;  // uniform: fk depends on k only
+        const int8_t *Ek = reinterpret_cast<const int8_t *>(smem) + (wave * fw + k) * W.esz;
+        uint8_t *ob = A.out_bits + (size_t)fk * A.bit_bytes;
+        for (int w = 0; w < nwords; ++w) {
+            const int j = (w << 6) + lane;
+            const unsigned long long mask = __ballot(j < n && Ek[j] < 0);
+            if (lane < 8) {
+                const int byte = (w << 3) + lane;
+                if (byte < A.bit_bytes)
+                    ob[byte] = (uint8_t)(mask >> (8 * lane));
+            }
+        }
+    }
+    if (valid && lane == lane0) {
+        A.out_conv[f] = (uint8_t)conv;
+        if (A.out_iters)
+            A.out_iters[f] = iters;
+    }
+    if (A.out_L && valid) {
+        int8_t *oL = A.out_L + (size_t)f * C.n_blocks * z;
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+#pragma unroll
+            for (int i = 0; i < DH; ++i) {
+                const int blk = A.lane_tab[(b * DH + i) * 2 + G.h].w;
+                if (blk >= 0) {
+                    oL[(size_t)blk * z + G.r] = (int8_t)Lr[b][i].x;
+                    oL[(size_t)blk * z + G.r + hz] = (int8_t)Lr[b][i].y;
+                }
+            }
+    }
+    if (A.out_E && valid)
+        for (int j = lf; j < n; j += z)
+            A.out_E[(size_t)f * n + j] = (int16_t)E[j];
+}
+
 template <int DMIN, int DMAX, int MB, int RULE>
 hipError_t launch_one_reg(const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
 {
+    if (A.frames_per_wg > 0) {
+        const int fw = 64 / C.z, wthreads = 64 * (A.frames_per_wg / fw);
+        const size_t wlds = wave_lds_bytes(C.n, C.z, A.syn_bytes, A.frames_per_wg, wthreads, MB, DMAX / 2);
+        if (wlds > 65536) {
+            hipError_t e = allow_max_lds<k_decode_wave_reg<DMIN, DMAX, MB, RULE>>();
+            if (e != hipSuccess)
+                return e;
+        }
+        const int grid = (A.n_frames + A.frames_per_wg - 1) / A.frames_per_wg;
+        auto wkern = k_decode_wave_reg<DMIN, DMAX, MB, RULE>;
+        hipLaunchKernelGGL(wkern, dim3(grid), dim3(wthreads), wlds, s, C, A);
+        return hipGetLastError();
+    }
     const bool persistent = A.persistent_wgs > 0;
     auto kern = persistent ? k_decode_reg_persistent<DMIN, DMAX, MB, RULE> : k_decode_frame_reg<DMIN, DMAX, MB, RULE>;
     if (lds > 65536) {
@@ -399,6 +618,12 @@ hipError_t launch_rule_reg(int rule, const DevCode &C, const DecodeArgs &A, int 
 }
 
 } // namespace
+
+size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw)
+{
+    const int fw = 64 / z;
+    return wave_lds_bytes(n, z, syn_bytes, fpw, 64 * (fpw / fw), kRegLayers, 10);
+}
 
 hipError_t launch_decode_reg(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {

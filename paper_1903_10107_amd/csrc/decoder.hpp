@@ -31,6 +31,7 @@ struct DecodeArgs {
     const int4 *lane_tab; // split kernel: [mb][DMAX/2][2] {c*Z | shift, c*Z, pad mask, block}
     const int32_t *blk2slot; // split kernel: block -> byte offset of its slot in a row pair's L slice
     int persistent_wgs;   // > 0: that many persistent workgroups pull frames from a queue
+    int frames_per_wg;    // > 0 (split_reg, Z <= 64): frames per workgroup, one wave per 64 / Z frames
     int *queue;           // persistent: device counter (reset by k_queue_reset)
     const int32_t *order; // persistent: decode order, a permutation of the frames, or nullptr
     int *mflags;          // layer-synchronous family: per frame {active, unsat, iterations, -}
@@ -60,6 +61,8 @@ hipError_t launch_decode_scalar(const LaunchPlan &P, const DevCode &C, const Dec
 hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_reg(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
+// LDS bytes of the split_reg decode with fpw frames per workgroup (Z <= 64)
+size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw);
 hipError_t launch_decode_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 // The layer-synchronous decode in three phases, for callers that stop early:
 // stage-in and the iteration-0 check; iterations t0..t1; stage-out.

@@ -15,7 +15,15 @@ a representative batch held on the GPU and keeps the fastest:
 * graph: the decode captured once as a HIP graph and replayed, or launched
   directly;
 * early stop (layer-synchronous family only): the host reads the number of
-  frames not yet retired after every iteration and stops launching at 0.
+  frames not yet retired after every iteration and stops launching at 0;
+* frames per workgroup (register-resident family, lifts Z <= 64): one frame
+  per workgroup, or 64 / Z frames per wave and 1 to 16 waves per workgroup.
+
+The row tile is the family's: one row per lane (lds, global), a row pair per
+lane (pairs), a row pair per two lanes with the messages in LDS (split), in a
+global slice (split_global_l) or in registers (split_reg), or a layer's row
+pairs spread over several workgroups (layer_sync); `row_tile()` names it for
+each candidate.
 
 Every candidate must produce identical outputs (the schedule never changes the
 results); a mismatch raises. Results are cached in a JSON file keyed by the
@@ -44,6 +52,20 @@ class Schedule:
     order: str = "none"          # "none", "hardest_first" (caller's difficulty) or "unsat_first"
     graph: bool = False
     check_every: int = 0         # layer-synchronous family: iterations between host checks (0: none)
+    frames_per_workgroup: int = 0  # split_reg with Z <= 64: frames per workgroup (0: one, with barriers)
+
+
+ROW_TILES = {"global": "1 row per lane, state in global memory",
+             "lds": "1 row per lane, state in LDS",
+             "pairs": "2 rows (r, r + Z/2) per lane, all edges, state in LDS",
+             "split": "2 rows per 2 lanes (half the edges each), E and L in LDS",
+             "split_global_l": "2 rows per 2 lanes, E in LDS, L streamed from a global slice",
+             "split_reg": "2 rows per 2 lanes, E in LDS, L in registers",
+             "layer_sync": "2 rows per 2 lanes, a layer spread over Z/1024 workgroups per frame"}
+
+
+def row_tile(family: str) -> str:
+    return ROW_TILES.get(family, family)
 
 
 def _key(base, z, n_frames, max_iter, acc_bits, has_difficulty) -> str:
@@ -55,8 +77,12 @@ def _key(base, z, n_frames, max_iter, acc_bits, has_difficulty) -> str:
     return h.hexdigest()[:24]
 
 
-def candidates(n_cu: int, has_difficulty: bool) -> list[Schedule]:
+def candidates(n_cu: int, has_difficulty: bool, z: int = 0) -> list[Schedule]:
     out = []
+    if 0 < z <= 64:
+        fw = 64 // z
+        for waves in (1, 2, 4, 8, 16):
+            out.append(Schedule("split_reg", 0, "none", False, 0, fw * waves))
     for kernel in ("split_reg", "split", "split_global_l", "layer_sync", "pairs", "lds", "global"):
         out.append(Schedule(kernel, 0, "none", False))
         out.append(Schedule(kernel, 0, "none", True))
@@ -78,6 +104,8 @@ class Runner:
         self.code = B.Code(base, z, acc_bits=acc_bits, kernel=sched.kernel, **code_kw)
         if sched.persistent_workgroups and self.code.plan()["kernel"] not in B.PERSISTENT_FAMILIES:
             raise B.LdpcError(B.LDPC_EUNSUPPORTED, "persistent schedule needs the split family")
+        if sched.frames_per_workgroup and (self.code.plan()["kernel"] != "split_reg" or z > 64):
+            raise B.LdpcError(B.LDPC_EUNSUPPORTED, "frames per workgroup need split_reg with Z <= 64")
         F = llr.shape[0]
         self.F = F
         self.syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
@@ -101,7 +129,8 @@ class Runner:
         self.batch = None
         if sched.graph:
             self.batch = B.Batch(self.code, self.syn, self.llr, F, max_iter, self.bits, self.conv, self.iters,
-                                 sched.persistent_workgroups, self.order, self.ws, check_every=sched.check_every)
+                                 sched.persistent_workgroups, self.order, self.ws, check_every=sched.check_every,
+                                 frames_per_workgroup=sched.frames_per_workgroup)
 
     def __call__(self):
         if self.unsat is not None:
@@ -111,7 +140,8 @@ class Runner:
         else:
             B.ldpc_decode_batch_sched(self.code, self.syn, self.llr, self.F, self.max_iter, self.bits, self.conv,
                                       self.iters, self.sched.persistent_workgroups, self.order, self.ws,
-                                      check_every=self.sched.check_every)
+                                      check_every=self.sched.check_every,
+                                      frames_per_workgroup=self.sched.frames_per_workgroup)
 
     def outputs(self):
         return self.bits.cpu().numpy(), self.conv.cpu().numpy(), self.iters.cpu().numpy()
@@ -147,7 +177,7 @@ def tune(base, z, syn, llr, max_iter, *, difficulty=None, acc_bits=0, cache_path
         if key in cache:
             return cache[key]
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    cands = cands if cands is not None else candidates(n_cu, difficulty is not None)
+    cands = cands if cands is not None else candidates(n_cu, difficulty is not None, int(z))
     results, ref = [], None
     for sched in cands:
         try:
@@ -162,7 +192,8 @@ def tune(base, z, syn, llr, max_iter, *, difficulty=None, acc_bits=0, cache_path
             ref = out
         elif not all(np.array_equal(a, b) for a, b in zip(ref, out)):
             raise RuntimeError(f"schedule {sched} changed the decoded results")
-        results.append({"schedule": asdict(sched), "ms": round(ms, 4)})
+        results.append({"schedule": asdict(sched), "row_tile": row_tile(run.code.plan()["kernel"]),
+                        "ms": round(ms, 4)})
         del run
     if not results:
         raise RuntimeError("no schedule applies")

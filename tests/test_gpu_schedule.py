@@ -248,3 +248,68 @@ def test_layer_sync_frame_limit_is_an_argument_error(B):
     with pytest.raises(B.LdpcError) as ei:
         B.ldpc_decode_batch_sched(gc, syn, llr, F, 10, bits, conv, iters)
     assert ei.value.code == B.LDPC_EINVAL
+
+
+@pytest.mark.parametrize("z,fpw", [(32, 2), (32, 8), (32, 32), (64, 1), (64, 16)])
+def test_frames_per_workgroup_matches_oracle(B, z, fpw):
+    """Several frames per workgroup (a frame's lanes inside one wave, no
+    workgroup barrier) give the oracle's results; frames of one wave converge at
+    different iterations, one cannot converge, and the frame count is not a
+    multiple of the frames per workgroup."""
+    import torch
+    code = I.Code(I.make_base(5, 32, z), z)
+    F = 37
+    q = np.where(np.arange(F) % 4 == 0, 0.03, 0.01)
+    q[5] = 0.3
+    fr = I.make_frames(code, F, q, 4040 + z)
+    gc = B.Code(code.base, code.z)
+    assert gc.plan()["kernel"] == "split_reg"
+    ref = O.decode(code.base, code.z, fr.syn, fr.llr, 30)
+    assert ref["conv"][5] == 0 and len(set(ref["iters"].tolist())) > 3
+    _say(f"[gpu fpw] z={z} frames_per_workgroup={fpw}")
+    syn, llr = torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda()
+    bits, conv, iters = _outs(code, F)
+    B.ldpc_decode_batch_sched(gc, syn, llr, F, 30, bits, conv, iters, frames_per_workgroup=fpw)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+    assert np.array_equal(conv.cpu().numpy(), ref["conv"])
+    assert np.array_equal(iters.cpu().numpy(), ref["iters"])
+    # the same schedule as a replayed graph, and with no iteration at all
+    batch = B.Batch(gc, syn, llr, F, 30, bits, conv, iters, frames_per_workgroup=fpw)
+    for rep in range(2):
+        bits.zero_()
+        iters.fill_(-1)
+        batch.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(bits.cpu().numpy(), ref["bits"]), rep
+        assert np.array_equal(iters.cpu().numpy(), ref["iters"]), rep
+    del batch
+    ref0 = O.decode(code.base, code.z, fr.syn, fr.llr, 0)
+    B.ldpc_decode_batch_sched(gc, syn, llr, F, 0, bits, conv, iters, frames_per_workgroup=fpw)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits.cpu().numpy(), ref0["bits"])
+    assert np.array_equal(conv.cpu().numpy(), ref0["conv"])
+
+
+def test_frames_per_workgroup_argument_errors(B):
+    import torch
+    code = I.Code(I.make_base(5, 32, 32), 32)
+    fr = I.make_frames(code, 4, 0.01, 3)
+    syn, llr = torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda()
+    bits, conv, iters = _outs(code, 4)
+    gc = B.Code(code.base, code.z)
+    for kw, rc in (({"frames_per_workgroup": 3}, B.LDPC_EINVAL),            # not a multiple of 64 / z
+                   ({"frames_per_workgroup": 34}, B.LDPC_EINVAL),           # 17 waves
+                   ({"frames_per_workgroup": -2}, B.LDPC_EINVAL),
+                   ({"frames_per_workgroup": 2, "persistent_workgroups": 4}, B.LDPC_EINVAL)):
+        with pytest.raises(B.LdpcError) as ei:
+            B.ldpc_decode_batch_sched(gc, syn, llr, 4, 10, bits, conv, iters, **kw)
+        assert ei.value.code == rc, kw
+    big = I.Code(I.make_base(5, 32, 256), 256)
+    gb = B.Code(big.base, big.z)
+    frb = I.make_frames(big, 2, 0.01, 3)
+    bb, cb, ib = _outs(big, 2)
+    with pytest.raises(B.LdpcError) as ei:
+        B.ldpc_decode_batch_sched(gb, torch.from_numpy(frb.syn).cuda(), torch.from_numpy(frb.llr).cuda(), 2, 10,
+                                  bb, cb, ib, frames_per_workgroup=2)
+    assert ei.value.code == B.LDPC_EUNSUPPORTED
