@@ -102,13 +102,20 @@ int ldpc_code_create(const int32_t *base, int32_t mb, int32_t nb, int32_t z,
 /* Release a handle (NULL is ignored). No decode may be in flight on it. */
 void ldpc_code_destroy(ldpc_code *code);
 
-/* Sizes of a code: n = nb*z variable nodes, m = mb*z checks, n_edges = n_blocks*z;
+/* Sizes of a code (Sec. 4.1: a QC code of an mb x nb base lifted by z):
+ * n = nb*z variable nodes, m = mb*z checks, n_edges = n_blocks*z;
  * has_4cycles = 1 if two base rows and two base columns close a length-4 cycle
  * after lifting. Any output pointer may be NULL. */
 int ldpc_code_dims(const ldpc_code *code, int32_t *n, int32_t *m, int64_t *n_edges,
                    int32_t *n_blocks, int32_t *has_4cycles);
 
-/* Decode a batch of frames.
+/* Decode a batch of frames: the layered decoder of Sec. 2 (layers in ascending
+ * base-row order; per check row the VN->CN messages of Eq. 8, the check node of
+ * Eqs. 1 and 4 by the integer tau of Alg. 1 (Sec. 3.2) in the rule's fold order,
+ * the soft-value update of Eq. 9 under the saturation rule of Alg. 2 (Sec. 3.3);
+ * the syndrome test H x^ = s before the first iteration and after each one,
+ * stopping a frame as soon as it holds). One frame's result does not depend on
+ * the other frames of the batch, on the kernel family or on the schedule.
  * syndromes: DEVICE uint8 [n_frames][ceil(m/8)], Alice's s = Hx, packed.
  * llr_in:    DEVICE int8 [n_frames][n], Bob's channel soft values, positive =
  *            bit 0; -128 is read as -127.
@@ -122,7 +129,9 @@ int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int
                       int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
                       uint8_t *out_converged, void *stream);
 
-/* As ldpc_decode_batch, plus optional outputs (each may be NULL):
+/* As ldpc_decode_batch (Secs. 2 and 3), plus the decoder state the paper keeps
+ * (Sec. 2: only the soft values E and the CN->VN messages L are stored) and
+ * optional outputs (each may be NULL):
  * out_iters: DEVICE int32 [n_frames]: iterations run (0 = converged at the
  *            pre-check; max_iter when not converged).
  * out_L:     DEVICE int8 [n_frames][n_blocks][z]: final CN->VN messages, blocks
@@ -205,7 +214,9 @@ typedef struct {
                                       (LDPC_EUNSUPPORTED / LDPC_EINVAL otherwise). */
 } ldpc_schedule;
 
-/* ldpc_decode_batch_ex with a schedule (NULL = default). The decoded results do
+/* ldpc_decode_batch_ex with a schedule (NULL = default): frames are independent
+ * (the paper's inter-frame parallel scheme, Sec. 4.2), so the schedule only
+ * places them on the GPU. The decoded results do
  * not depend on the schedule. The workspace must hold
  * ldpc_workspace_bytes_sched(code, n_frames, sched) bytes (a persistent schedule
  * needs 256 bytes for its queue); NULL allocates it stream-ordered.
