@@ -987,7 +987,7 @@ def main():
                     help="frames of the reveal-and-retry figure on the ragged batch (0: skip)")
     ap.add_argument("--no-large", action="store_true", help="skip the n = 1048576 figure")
     ap.add_argument("--small-frames", default="64,65536",
-                    help="batch sizes of the n = 1024 short-frame figure (empty: skip)")
+                    help="batch sizes of the n = 1024 short-frame figure (0: skip)")
     ap.add_argument("--syndrome-frames", type=int, default=4096,
                     help="frames of the syndrome-encoder figure (Alice's side; 0: skip)")
     ap.add_argument("--pipelined-streams", type=int, default=3,
@@ -1128,8 +1128,9 @@ def main():
         out["syndrome"] = syndrome_figure(args.syndrome_frames, args.steps, args.warmup)
     if not args.no_large:
         out["large"] = large_frames(args.steps, args.warmup)
-    if args.small_frames:
-        out["small"] = small_frames([int(v) for v in args.small_frames.split(",") if v], args.steps, args.warmup)
+    small_batches = [int(v) for v in args.small_frames.split(",") if v.strip() and int(v) > 0]
+    if small_batches:
+        out["small"] = small_frames(small_batches, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(code, fr, wl, args.cpu_seconds)
         if not args.no_large:

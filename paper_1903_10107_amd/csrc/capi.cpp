@@ -124,14 +124,14 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     // table, one lane pair per row
     // pair (Z <= 1024), E byte addresses below 2^16. LDS: E plus the dummy block
     // column, the syndrome, the per-lane address table [threads][mb][dh] of
-    // 16-bit entries, three vote words and the queue slot.
+    // 16-bit entries, three vote words, the queue slot and two last-layer test words.
     if ((hint == 0 || hint == LDPC_HINT_SPLIT_REG) && split_ok && h.mb == 5 && dmax == 20 && h.min_deg >= 19 &&
         h.acc_bits == 8 && h.e_max > h.msg_max &&
         h.offsets.empty() && h.z <= 1024 && (size_t)h.n + h.z <= 65536) {
         const int threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
         const size_t e_sp = round_up((size_t)h.n + h.z, 16);
         const size_t tab = round_up((size_t)h.mb * dh * threads * 2, 16);
-        const size_t total = e_sp + round_up(syn_bytes, 16) + tab + 16;
+        const size_t total = e_sp + round_up(syn_bytes, 16) + tab + 32;
         if (total <= (size_t)lds_limit) {
             P.split_reg = true;
             P.split_dmax = dmax;

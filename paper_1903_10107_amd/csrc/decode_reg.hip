@@ -44,7 +44,7 @@ struct RegLds {
     int8_t *E;        // [n + Z] soft values plus the dummy block column, at LDS offset 0
     uint8_t *syn;     // packed syndrome of the current frame
     uint16_t *addr;   // [threads][MB][DH] E byte address of each lane's slot
-    int *flags;       // three vote words and one queue slot
+    int *flags;       // three vote words, the queue slot, two last-layer test words
 };
 
 __device__ __forceinline__ RegLds reg_lds(const DecodeArgs &A)
@@ -167,10 +167,13 @@ __device__ __forceinline__ int reg_unsat(const RegLds &M, const RegLane &G, unsi
 // Eq. 8, the check node (Eqs. 1 and 4 by Alg. 1 in forward-backward order, or
 // min-sum) and Eq. 9 under Alg. 2 for one lane's slots of a row pair in layer
 // b; lk holds the row pair's messages of that layer and receives the new ones.
-template <int DMIN, int DMAX, int RULE>
-__device__ __forceinline__ void reg_finish(const DevCode &C, const RegLane &G, int b, const s16x2 (&e)[DMAX / 2],
-                                           const unsigned (&a0)[DMAX / 2], s16x2 (&lk)[DMAX / 2], s16x2 syn,
-                                           unsigned hzb)
+// With PAR, also the syndrome test of the row pair on the new soft values: 1 when
+// a row fails. (Used on the last layer, whose variable nodes take their final
+// value of the iteration there.)
+template <int DMIN, int DMAX, int RULE, bool PAR = false>
+__device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, int b, const s16x2 (&e)[DMAX / 2],
+                                          const unsigned (&a0)[DMAX / 2], s16x2 (&lk)[DMAX / 2], s16x2 syn,
+                                          unsigned hzb)
 {
     constexpr int DH = DMAX / 2;
     const s16x2 em = splat2(C.e_max);
@@ -206,6 +209,7 @@ __device__ __forceinline__ void reg_finish(const DevCode &C, const RegLane &G, i
     const s16x2 par = syn ^ own ^ swap_pair(own);
     u16x2 out[DH];
     pair_fold<DH, RULE>(p, out);
+    s16x2 own_o = splat2(0);
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
         const s16x2 sg = (par ^ vg[i]) >> (short)15;  // -1 in a half whose message is negative
@@ -215,7 +219,14 @@ __device__ __forceinline__ void reg_finish(const DevCode &C, const RegLane &G, i
         lds_st<int8_t>(a0[i], (int8_t)o.x);
         lds_st<int8_t>(a0[i] ^ hzb, (int8_t)o.y);
         lk[i] = ln;
+        if constexpr (PAR)
+            own_o ^= split_pad_slot<DMIN, DMAX>(i) ? (o & __builtin_bit_cast(s16x2, real_mask<DH>(G, b, i))) : o;
     }
+    if constexpr (PAR) {
+        const s16x2 pe = syn ^ own_o ^ swap_pair(own_o);
+        return G.active && (pe.x | pe.y) < 0;
+    }
+    return 0;
 }
 
 // Decode frame f with one workgroup (address table already built).
@@ -233,7 +244,7 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
     for (int i = tid; i < A.syn_bytes; i += nthr)
         M.syn[i] = syn[i];
     stage_llr<int8_t>(M.E, A.llr + (size_t)f * n, n, C.e_max < 127 ? C.e_max : 127, tid, nthr);
-    if (tid < 3)
+    if (tid < 6 && tid != 3)  // vote words 0-2 and the last-layer test words 4-5 (3 is the queue slot)
         M.flags[tid] = 0;
     __syncthreads();
 
@@ -259,6 +270,14 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
         for (int i = 0; i < DH; ++i)
             Lr[b][i] = splat2(0);
 
+    // The syndrome test of the state after iteration t-1 starts from its last
+    // layer: that layer's variable nodes take their final value of the
+    // iteration in it, so its rows are tested on the values it writes, and a
+    // failing lane sets word 4 + (t-1) % 2 before the barrier that opens
+    // iteration t. Only when no last-layer row failed (rare before convergence)
+    // are the other layers tested, layer 0 on the values it loads anyway,
+    // and voted on; otherwise the test costs no barrier of its own. Thread 0
+    // clears the word after the next barrier, which every reader has passed.
     for (int t = 1; t <= A.max_iter && !conv; ++t) {
         bool stop = false;
 #pragma unroll
@@ -268,21 +287,28 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
             unsigned a0[DH];
             reg_addr<MB, DH>(M, G, b, a0);
             __syncthreads();
+            if (b == 1 && t >= 2 && tid == 0)
+                M.flags[4 + ((t - 1) & 1)] = 0;
             s16x2 e[DH];
             reg_fetch<DH>(M, a0, hzb, e);
-            if (b == 0 && t >= 2) {
+            if (b == 0 && t >= 2 && !M.flags[4 + ((t - 1) & 1)]) {
                 const s16x2 own = reg_parity<DMIN, DMAX>(G, 0, e);
                 const s16x2 pe = reg_syn(synm, 0) ^ own ^ swap_pair(own);
-                const int fail0 = G.active && (pe.x | pe.y) < 0;
-                if (!block_vote(fail0, M.flags, vk) &&
-                    !block_vote(reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 1, MB), M.flags, vk)) {
+                const int fail = (G.active && (pe.x | pe.y) < 0) |
+                                 reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 1, MB - 1);
+                if (!block_vote(fail, M.flags, vk)) {
                     conv = 1;
                     iters = t - 1;
                     stop = true;
                     break;
                 }
             }
-            reg_finish<DMIN, DMAX, RULE>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb);
+            if (b == MB - 1) {
+                if (reg_finish<DMIN, DMAX, RULE, true>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb))
+                    M.flags[4 + (t & 1)] = 1;
+            } else {
+                reg_finish<DMIN, DMAX, RULE>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb);
+            }
         }
         if (stop)
             break;
