@@ -80,17 +80,26 @@ __device__ __forceinline__ RegLane reg_setup(const DevCode &C, const DecodeArgs 
     G.active = G.r < hz;
     G.real = 0;
     const unsigned zm = (unsigned)(C.z - 1), dummy = (unsigned)(C.nb * C.z);
+    // Every lane reads its entries (the table has both halves of every slot),
+    // so that the loads do not sit in a branch that waits for each in turn; one
+    // layer's entries at a time (an empty asm statement that may touch memory
+    // keeps the layers' loads apart), so that they are in flight together
+    // without holding all layers' entries in registers.
 #pragma unroll
-    for (int b = 0; b < MB; ++b)
+    for (int b = 0; b < MB; ++b) {
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int i = 0; i < DH; ++i) {
             const int4 te = A.lane_tab[(b * DH + i) * 2 + G.h];
             const bool real = G.active && te.z != 0;
-            const unsigned a0 = G.active ? (((unsigned)G.r + (unsigned)te.x) & zm) | (unsigned)te.y : dummy;
-            M.addr[G.tid * (MB * DH) + b * DH + i] = (uint16_t)a0;
-            if (real)
-                G.real |= 1ull << (b * DH + i);
+            const unsigned a1 = (((unsigned)G.r + (unsigned)te.x) & zm) | (unsigned)te.y;
+            M.addr[G.tid * (MB * DH) + b * DH + i] = (uint16_t)(G.active ? a1 : dummy);
+            G.real |= (uint64_t)real << (b * DH + i);
         }
+    }
+    // the mask is complete here (otherwise its bits are formed where it is first
+    // used, and the table entries stay live, in scratch, until then)
+    __asm__ volatile("" : "+v"(G.real));
     return G;
 }
 
@@ -124,16 +133,51 @@ __device__ __forceinline__ void reg_addr(const RegLds &M, const RegLane &G, int 
     }
 }
 
+// Hands the zero-extended 32-bit addresses to an empty asm statement, so that
+// a use in a later basic block (after a layer barrier) does not mask them to 16
+// bits again. The statement waits for the loads: place it where they are
+// complete anyway (at a barrier, after the E writes).
+template <int DH>
+__device__ __forceinline__ void reg_pin(unsigned (&a0)[DH])
+{
+#pragma unroll
+    for (int i = 0; i < DH; ++i)
+        __asm__ volatile("" : "+v"(a0[i]));
+}
+
+// a ^ b ^ c in one instruction (v_bitop3_b32 with truth table 0x96; the
+// compiler keeps a chain of two-input XORs otherwise)
+__device__ __forceinline__ s16x2 xor3(s16x2 a, s16x2 b, s16x2 c)
+{
+    return __builtin_bit_cast(s16x2, __builtin_amdgcn_bitop3_b32(__builtin_bit_cast(unsigned, a),
+                                                                 __builtin_bit_cast(unsigned, b),
+                                                                 __builtin_bit_cast(unsigned, c), 0x96));
+}
+
+// XOR of x[0 .. N-1], two operands per instruction
+template <int N>
+__device__ __forceinline__ s16x2 xor_all(const s16x2 (&x)[N])
+{
+    s16x2 acc = x[0];
+    int i = 1;
+#pragma unroll
+    for (; i + 1 < N; i += 2)
+        acc = xor3(acc, x[i], x[i + 1]);
+    if (i < N)
+        acc ^= x[i];
+    return acc;
+}
+
 // XOR over this lane's real slots of the soft values' sign bits
 template <int DMIN, int DMAX>
 __device__ __forceinline__ s16x2 reg_parity(const RegLane &G, int b, const s16x2 (&e)[DMAX / 2])
 {
     constexpr int DH = DMAX / 2;
-    s16x2 own = splat2(0);
+    s16x2 t[DH];
 #pragma unroll
     for (int i = 0; i < DH; ++i)
-        own ^= split_pad_slot<DMIN, DMAX>(i) ? (e[i] & __builtin_bit_cast(s16x2, real_mask<DH>(G, b, i))) : e[i];
-    return own;
+        t[i] = split_pad_slot<DMIN, DMAX>(i) ? (e[i] & __builtin_bit_cast(s16x2, real_mask<DH>(G, b, i))) : e[i];
+    return xor_all<DH>(t);
 }
 
 // layer b's pair of syndrome bits as the sign bits of two 16-bit halves (bit b:
@@ -159,7 +203,7 @@ __device__ __forceinline__ int reg_unsat(const RegLds &M, const RegLane &G, unsi
         reg_addr<MB, DH>(M, G, b, a0);
         reg_fetch<DH>(M, a0, hzb, e);
         const s16x2 own = reg_parity<DMIN, DMAX>(G, b, e);
-        any |= reg_syn(synm, b) ^ own ^ swap_pair(own);
+        any |= xor3(reg_syn(synm, b), own, swap_pair(own));
     }
     return G.active && (any.x | any.y) < 0;
 }
@@ -180,7 +224,6 @@ __device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, in
     const u16x2 mm = usplat2(C.msg_max), kf = usplat2(16384 - C.e_max * C.e_max);
     s16x2 vg[DH];
     u16x2 p[DH];
-    s16x2 own = splat2(0);
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
         // Eq. 8, saturated to the 8-bit soft-value range
@@ -202,14 +245,15 @@ __device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, in
             pi = (pi & mk) | (usplat2(kPad) & ~mk);
         }
         vg[i] = x;
-        own ^= x;
         p[i] = pi;
     }
-    // sign product of Eq. 1 over the whole row, times the syndrome bit
-    const s16x2 par = syn ^ own ^ swap_pair(own);
+    // sign product of Eq. 1 over the whole row, times the syndrome bit (x has
+    // the sign of v)
+    const s16x2 own = xor_all<DH>(vg);
+    const s16x2 par = xor3(syn, own, swap_pair(own));
     u16x2 out[DH];
     pair_fold<DH, RULE>(p, out);
-    s16x2 own_o = splat2(0);
+    s16x2 ot[DH];
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
         const s16x2 sg = (par ^ vg[i]) >> (short)15;  // -1 in a half whose message is negative
@@ -220,10 +264,11 @@ __device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, in
         lds_st<int8_t>(a0[i] ^ hzb, (int8_t)o.y);
         lk[i] = ln;
         if constexpr (PAR)
-            own_o ^= split_pad_slot<DMIN, DMAX>(i) ? (o & __builtin_bit_cast(s16x2, real_mask<DH>(G, b, i))) : o;
+            ot[i] = split_pad_slot<DMIN, DMAX>(i) ? (o & __builtin_bit_cast(s16x2, real_mask<DH>(G, b, i))) : o;
     }
     if constexpr (PAR) {
-        const s16x2 pe = syn ^ own_o ^ swap_pair(own_o);
+        const s16x2 own_o = xor_all<DH>(ot);
+        const s16x2 pe = xor3(syn, own_o, swap_pair(own_o));
         return G.active && (pe.x | pe.y) < 0;
     }
     return 0;
@@ -241,9 +286,29 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
 
     // stage in: syndrome, E = llr (-128 read as -127), vote words
     const uint8_t *syn = A.syn + (size_t)f * A.syn_bytes;
-    for (int i = tid; i < A.syn_bytes; i += nthr)
-        M.syn[i] = syn[i];
-    stage_llr<int8_t>(M.E, A.llr + (size_t)f * n, n, C.e_max < 127 ? C.e_max : 127, tid, nthr);
+    const int8_t *llr = A.llr + (size_t)f * n;
+    const int n16 = n >> 4;
+    if (C.e_max >= 127 && (n & 15) == 0 && ((uintptr_t)llr & 15) == 0 && n16 <= 2 * nthr &&
+        A.syn_bytes <= nthr) {
+        // at most two 16-byte LLR chunks and one syndrome byte per thread: all
+        // loads issued (at clamped, always valid indices) before any LDS write
+        const uint4 *src = reinterpret_cast<const uint4 *>(llr);
+        const int q0 = tid, q1 = tid + nthr;
+        const uint4 v0 = src[q0 < n16 ? q0 : n16 - 1];
+        const uint4 v1 = src[q1 < n16 ? q1 : n16 - 1];
+        const uint8_t sb = syn[tid < A.syn_bytes ? tid : A.syn_bytes - 1];
+        uint4 *dst = reinterpret_cast<uint4 *>(M.E);
+        if (q0 < n16)
+            dst[q0] = llr_no_m128(v0);
+        if (q1 < n16)
+            dst[q1] = llr_no_m128(v1);
+        if (tid < A.syn_bytes)
+            M.syn[tid] = sb;
+    } else {
+        for (int i = tid; i < A.syn_bytes; i += nthr)
+            M.syn[i] = syn[i];
+        stage_llr<int8_t>(M.E, llr, n, C.e_max < 127 ? C.e_max : 127, tid, nthr);
+    }
     if (tid < 6 && tid != 3)  // vote words 0-2 and the last-layer test words 4-5 (3 is the queue slot)
         M.flags[tid] = 0;
     __syncthreads();
@@ -286,6 +351,7 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
             // layer's E writes; after it only the E reads remain
             unsigned a0[DH];
             reg_addr<MB, DH>(M, G, b, a0);
+            reg_pin<DH>(a0);
             __syncthreads();
             if (b == 1 && t >= 2 && tid == 0)
                 M.flags[4 + ((t - 1) & 1)] = 0;
@@ -293,7 +359,7 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
             reg_fetch<DH>(M, a0, hzb, e);
             if (b == 0 && t >= 2 && !M.flags[4 + ((t - 1) & 1)]) {
                 const s16x2 own = reg_parity<DMIN, DMAX>(G, 0, e);
-                const s16x2 pe = reg_syn(synm, 0) ^ own ^ swap_pair(own);
+                const s16x2 pe = xor3(reg_syn(synm, 0), own, swap_pair(own));
                 const int fail = (G.active && (pe.x | pe.y) < 0) |
                                  reg_unsat<DMIN, DMAX, MB>(M, G, synm, hzb, 1, MB - 1);
                 if (!block_vote(fail, M.flags, vk)) {
@@ -322,18 +388,29 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
     if (!conv)
         iters = A.max_iter;
 
-    // stage out: hard decisions (wavefront ballot), flag, count, optional state
-    const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
-    const int nwords = (n + 63) >> 6;
+    // stage out: hard decisions, flag, count, optional state
     uint8_t *ob = A.out_bits + (size_t)f * A.bit_bytes;
-    for (int w = wv; w < nwords; w += nwv) {
-        const int j = (w << 6) + lane;
-        const bool neg = j < n && M.E[j] < 0;
-        const unsigned long long mask = __ballot(neg);
-        if (lane < 8) {
-            const int byte = (w << 3) + lane;
-            if (byte < A.bit_bytes)
-                ob[byte] = (uint8_t)(mask >> (8 * lane));
+    if ((n & 7) == 0) {
+        // one output byte per thread and step from an 8-byte LDS read
+        const uint2 *e8 = reinterpret_cast<const uint2 *>(M.E);
+#pragma unroll 4
+        for (int q = tid; q < (n >> 3); q += nthr) {
+            const uint2 w = e8[q];
+            ob[q] = (uint8_t)(sign_nibble(w.x) | sign_nibble(w.y) << 4);
+        }
+    } else {
+        // wavefront ballots over 64 soft values
+        const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+        const int nwords = (n + 63) >> 6;
+        for (int w = wv; w < nwords; w += nwv) {
+            const int j = (w << 6) + lane;
+            const bool neg = j < n && M.E[j] < 0;
+            const unsigned long long mask = __ballot(neg);
+            if (lane < 8) {
+                const int byte = (w << 3) + lane;
+                if (byte < A.bit_bytes)
+                    ob[byte] = (uint8_t)(mask >> (8 * lane));
+            }
         }
     }
     if (tid == 0) {
@@ -469,17 +546,19 @@ __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs 
     G.real = 0;
     {
         const unsigned ebase = (unsigned)(slot * W.esz), dummy = ebase + (unsigned)(C.nb * z);
+        // as in reg_setup: unconditional loads, one layer at a time
 #pragma unroll
-        for (int b = 0; b < MB; ++b)
+        for (int b = 0; b < MB; ++b) {
+            __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int i = 0; i < DH; ++i) {
                 const int4 te = A.lane_tab[(b * DH + i) * 2 + G.h];
-                const unsigned a0 =
-                    valid ? ebase + ((((unsigned)G.r + (unsigned)te.x) & zm) | (unsigned)te.y) : dummy;
-                M.addr[tid * (MB * DH) + b * DH + i] = (uint16_t)a0;
-                if (valid && te.z != 0)
-                    G.real |= 1ull << (b * DH + i);
+                const unsigned a1 = ebase + ((((unsigned)G.r + (unsigned)te.x) & zm) | (unsigned)te.y);
+                M.addr[tid * (MB * DH) + b * DH + i] = (uint16_t)(valid ? a1 : dummy);
+                G.real |= (uint64_t)(valid && te.z != 0) << (b * DH + i);
             }
+        }
+        __asm__ volatile("" : "+v"(G.real));
     }
     // 1 when some lane of this lane's frame has pred (a wave ballot)
     auto frame_any = [&](bool pred) -> bool { return ((__ballot(pred) >> lane0) & fmask) != 0; };
@@ -531,7 +610,7 @@ __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs 
                 // the state after iteration t-1: layer 0 from the values just read,
                 // the other layers only for frames whose layer 0 holds
                 const s16x2 own = reg_parity<DMIN, DMAX>(G, 0, e);
-                const s16x2 pe = reg_syn(synm, 0) ^ own ^ swap_pair(own);
+                const s16x2 pe = xor3(reg_syn(synm, 0), own, swap_pair(own));
                 const bool pass0 = !frame_any(valid && (pe.x | pe.y) < 0);
                 const bool need = !done && pass0;
                 if (__ballot(need) != 0) {

@@ -40,6 +40,29 @@ __device__ __forceinline__ int rot(int r, int s, int z)
 // Stage the frame's LLRs into E, clamped to [-lim, lim] (lim = min(E_max, 127)).
 // With int8 E, lim = 127 and 16-byte aligned rows, 16 bytes move per lane and
 // the only value to fix, -128, is found with an exact packed-byte zero test.
+// Sixteen int8 LLRs with every -128 replaced by -127.
+__device__ __forceinline__ uint4 llr_no_m128(uint4 v)
+{
+    unsigned *w = reinterpret_cast<unsigned *>(&v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned x = w[k] ^ 0x80808080u;  // bytes equal to 0x80 become 0
+        // exact per-byte zero test (no carry crosses a byte): 0x80 where x's byte is 0
+        const unsigned z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+        w[k] += z >> 7;  // 0x80 (-128) -> 0x81 (-127)
+    }
+    return v;
+}
+
+// Hard decisions [E_j < 0] of four int8 soft values (byte k of x is E_{4i+k})
+// as the low four bits, LSB first: the sign bits, moved to bits 0, 8, 16, 24,
+// are gathered into bits 24..27 by one multiplication (no carries: the partial
+// products occupy distinct bits).
+__device__ __forceinline__ unsigned sign_nibble(unsigned x)
+{
+    return (((x >> 7) & 0x01010101u) * 0x01020408u) >> 24;
+}
+
 template <typename ET>
 __device__ __forceinline__ void stage_llr(ET *E, const int8_t *__restrict__ llr, int n, int lim, int tid, int nthr)
 {
@@ -47,18 +70,8 @@ __device__ __forceinline__ void stage_llr(ET *E, const int8_t *__restrict__ llr,
         if (lim == 127 && (n & 15) == 0 && (((uintptr_t)llr) & 15) == 0) {
             const uint4 *src = reinterpret_cast<const uint4 *>(llr);
             uint4 *dst = reinterpret_cast<uint4 *>(E);
-            for (int q = tid; q < (n >> 4); q += nthr) {
-                uint4 v = src[q];
-                unsigned *w = reinterpret_cast<unsigned *>(&v);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const unsigned x = w[k] ^ 0x80808080u;  // bytes equal to 0x80 become 0
-                    // exact per-byte zero test (no carry crosses a byte): 0x80 where x's byte is 0
-                    const unsigned z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
-                    w[k] += z >> 7;  // 0x80 (-128) -> 0x81 (-127)
-                }
-                dst[q] = v;
-            }
+            for (int q = tid; q < (n >> 4); q += nthr)
+                dst[q] = llr_no_m128(src[q]);
             return;
         }
     }
