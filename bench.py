@@ -834,7 +834,10 @@ def operating_point(gc, wl, code, n_short, steps, warmup, fer_frames, with_lds=F
           "unit_bytes": f"{bytes_per_edge_iter} B per edge-iteration (L and E each read and written once) x "
                         f"{edge_iters:.0f} edge-iterations + {io_bytes} B frame I/O",
           "note": "HBM-equivalent: the decoder state stays in LDS and registers, so the measured HBM traffic "
-                  "(traffic) is the frame I/O; the kernel is bound by integer VALU issue (alu)",
+                  "(traffic) is the frame I/O; the kernel is bound by integer VALU issue (alu)" + (
+                      "; below 0.40 of the HBM roofline because a single launch lasts as long as its slowest "
+                      "frame (tail.cu_busy_frac); launches that do not wait for it (pipelined, batched) go higher"
+                      if achieved / HBM_PEAK_GBS < 0.40 else ""),
           "alu": {"achieved": round(alu_tops, 2), "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
                   "frac": round(alu_tops / ALU_PEAK_TOPS, 4), "algorithmic_ops_per_launch": int_ops,
                   "unit_ops": "14 int ops per edge-iteration + 27 per (row degree - 2) per check row-iteration; "
