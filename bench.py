@@ -355,7 +355,7 @@ def learned(steps_train, steps, warmup):
     36% shortened, 20 iterations: train per-iteration, per-edge offsets of the
     FP32 offset min-sum with the library's forward and backward kernels (Adam,
     512 frames per step from a fixed pool of 2048), quantize them to the
-    integer LLR step, and judge the integer decoder (min-sum + learned offsets)
+    integer LLR step, and evaluate the integer decoder (min-sum + learned offsets)
     against plain RCBP and plain min-sum on 4096 fresh frames."""
     import numpy as np
     import torch
@@ -433,10 +433,10 @@ def learned(steps_train, steps, warmup):
     decoders = (("rcbp", B.LDPC_RULE_RCBP_FB, None), ("minsum", B.LDPC_RULE_MINSUM, None),
                 ("minsum_learned", B.LDPC_RULE_MINSUM, offsets), ("rcbp_learned", B.LDPC_RULE_RCBP_FB, offsets))
     # at the training rate (36% shortened) ...
-    judged = {name: LN.evaluate(code, q, ns, max_iter=T, frames=4096, cn_rule=rule, offsets=off)
-              for name, rule, off in decoders}
+    evaluated = {name: LN.evaluate(code, q, ns, max_iter=T, frames=4096, cn_rule=rule, offsets=off)
+                 for name, rule, off in decoders}
     # ... and at equal frame error rate: each decoder at its own least shortening
-    # with FER <= 1e-2 (bisection on 2048 frames, 64-position steps), judged on
+    # with FER <= 1e-2 (bisection on 2048 frames, 64-position steps), evaluated on
     # 4096 fresh frames, with its throughput on a 512-frame batch there
     equal_fer = {}
     for name, rule, off in decoders:
@@ -470,9 +470,9 @@ def learned(steps_train, steps, warmup):
         ms = tune.time_ms(run, max(3, steps // 5), max(1, warmup))
         bits, conv, _ = run.outputs()
         ok, _ = M.frame_outcomes(fr.x, I.unpack_bits(bits, code.n), conv)
-        judged[name]["mbit_s"] = round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2)
-        judged[name]["ms_per_batch"] = round(ms, 4)
-        judged[name]["kernel"] = run.code.plan()["kernel"]
+        evaluated[name]["mbit_s"] = round(float(fr.key_bits()[ok].sum()) / (ms / 1e3) / 1e6, 2)
+        evaluated[name]["ms_per_batch"] = round(ms, 4)
+        evaluated[name]["kernel"] = run.code.plan()["kernel"]
     return {"workload": "n8192_q2_learned", "code": "5x32 QC base, Z=256, column weight 3 (n=8192)",
             "qber": q, "short_frac": 0.36, "iterations": T, "train_steps": steps_train, "frames_per_step": F,
             "train_ms_per_step": round(train_ms, 3), "train_frames_per_s": round(F / (train_ms / 1e3), 1),
@@ -497,7 +497,7 @@ def learned(steps_train, steps, warmup):
                                           "frac_of_fp32_vector_peak": round(bwd_tops / 157.3, 4),
                                           "unit_ops": f"10 FP32 ops per edge-iteration x {edge_iters:.0f} "
                                                       "edge-iterations"}},
-            "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "judged_at_training_rate": judged,
+            "offsets_int_hist": np.bincount(offsets.ravel()).tolist(), "evaluated_at_training_rate": evaluated,
             "equal_fer": equal_fer,
             "note": "offsets learned on the FP32 offset min-sum relaxation; rcbp_learned applies the same "
                     "integer table to the RCBP check node (the paper's decoder has no trainable relaxation)"}

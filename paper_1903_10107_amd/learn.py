@@ -1,7 +1,7 @@
 """Learned offsets for the check node: train per-iteration, per-base-edge
 offsets of the differentiable FP32 offset min-sum (the library's forward and
 backward kernels) on synthetic frames, quantize them to the integer decoder's
-LLR step, and judge the integer decoder with them by frame error rate,
+LLR step, and evaluate the integer decoder with them by frame error rate,
 efficiency and iterations.
 
 Training inputs are the quantized channel LLRs the integer decoder sees,

@@ -57,7 +57,7 @@ def measure(code: I.Code, gcode: B.Code, base_frames: I.Frames, kappa: int, max_
 def search(code: I.Code, qber: float, *, frames: int = 2048, max_iter: int = 60, fer_target: float = 1e-2,
            step: int = 256, seed: int = 1903_10107, acc_bits: int = 0, log=None, **code_kw) -> OperatingPoint:
     """Largest kappa (to within step) whose batch FER is at most fer_target.
-    code_kw (cn_rule, offsets, ...) configures the integer decoder judged."""
+    code_kw (cn_rule, offsets, ...) configures the integer decoder evaluated."""
     gcode = B.Code(code.base, code.z, acc_bits=acc_bits, **code_kw)
     order = I.position_order(code)
     base = I.make_frames(code, frames, qber, seed)
