@@ -68,8 +68,8 @@ typedef struct {
                                subtracted from every CN message magnitude at iteration t using
                                row min(t-1, offset_iters-1), result clamped to [0, msg_max];
                                copied at create. NULL = no offsets (the paper's decoder).
-                               Every kernel family but LDPC_KERNEL_SPLIT_REG serves them
-                               (automatic selection then takes the next family). */
+                               Every kernel family serves them (LDPC_KERNEL_SPLIT_REG while
+                               its LDS holds the table; not with frames_per_workgroup). */
     int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
     int32_t kernel_hint;    /* 0: pick the kernel family automatically; LDPC_HINT_*: use that
                                family, or fail with LDPC_EUNSUPPORTED when it does not apply
@@ -157,7 +157,7 @@ int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const 
  *                      layer held in registers for the whole decode and E in
  *                      LDS (codes of five base rows, power-of-two z <= 1024,
  *                      rows of 19 or 20 edges, 8-bit soft values with
- *                      e_max > msg_max, no offset table).
+ *                      e_max > msg_max).
  * LDPC_KERNEL_LAYER_SYNC  one launch per layer over all frames, several
  *                      workgroups per frame, E and L in global slices per frame
  *                      (codes whose soft values do not fit in LDS, e.g. n = 2^20);
@@ -208,7 +208,8 @@ typedef struct {
     int32_t frames_per_workgroup;  /* 0: one frame per workgroup. > 0: that many frames per
                                       workgroup, each frame's z lanes inside one wave (64 / z
                                       frames per wave, no workgroup barrier); needs the
-                                      LDPC_KERNEL_SPLIT_REG family with z <= 64, a multiple of
+                                      LDPC_KERNEL_SPLIT_REG family with z <= 64 and no offset
+                                      table, a multiple of
                                       64 / z, at most 16 waves per workgroup, all frames' soft
                                       values within 64 KB of LDS, and no persistent schedule
                                       (LDPC_EUNSUPPORTED / LDPC_EINVAL otherwise). */

@@ -120,18 +120,19 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
     P.split_reg = false;
     // Split arithmetic with L in registers: five base rows, rows of 19 or 20 edges
     // (DMAX = 20), 8-bit soft values with E_max > MSG_max (the frozen test
-    // relies on a frozen E and its Eq. 8 value sharing a sign), no offset
-    // table, one lane pair per row
-    // pair (Z <= 1024), E byte addresses below 2^16. LDS: E plus the dummy block
-    // column, the syndrome, the per-lane address table [threads][mb][dh] of
-    // 16-bit entries, three vote words, the queue slot and two last-layer test words.
+    // relies on a frozen E and its Eq. 8 value sharing a sign), one lane pair per
+    // row pair (Z <= 1024), E byte addresses below 2^16. LDS: E plus the dummy
+    // block column, the syndrome, the per-lane address table [threads][mb][dh] of
+    // 16-bit entries, three vote words, the queue slot and two last-layer test
+    // words (32 bytes), then with an offset table its rows per layer, slot and
+    // lane half (4 bytes each).
     if ((hint == 0 || hint == LDPC_HINT_SPLIT_REG) && split_ok && h.mb == 5 && dmax == 20 && h.min_deg >= 19 &&
-        h.acc_bits == 8 && h.e_max > h.msg_max &&
-        h.offsets.empty() && h.z <= 1024 && (size_t)h.n + h.z <= 65536) {
+        h.acc_bits == 8 && h.e_max > h.msg_max && h.z <= 1024 && (size_t)h.n + h.z <= 65536) {
         const int threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
         const size_t e_sp = round_up((size_t)h.n + h.z, 16);
         const size_t tab = round_up((size_t)h.mb * dh * threads * 2, 16);
-        const size_t total = e_sp + round_up(syn_bytes, 16) + tab + 32;
+        const size_t offs = h.offsets.empty() ? 0 : (size_t)h.offset_iters * h.mb * dh * 2 * 4;
+        const size_t total = e_sp + round_up(syn_bytes, 16) + tab + 32 + offs;
         if (total <= (size_t)lds_limit) {
             P.split_reg = true;
             P.split_dmax = dmax;
@@ -304,9 +305,9 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
             return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup < 0");
         if (fpw > 0) {
             const int z = code->h.z;
-            if (!code->plan.split_reg || z > 64)
-                return fail(LDPC_EUNSUPPORTED,
-                            "ldpc_schedule: frames_per_workgroup needs the split_reg family with z <= 64");
+            if (!code->plan.split_reg || z > 64 || !code->h.offsets.empty())
+                return fail(LDPC_EUNSUPPORTED, "ldpc_schedule: frames_per_workgroup needs the split_reg family "
+                                               "with z <= 64 and no offset table");
             const int fw = 64 / z;
             if (fpw % fw != 0 || fpw / fw > 16)
                 return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup must be a multiple of 64 / z, "

@@ -1,7 +1,7 @@
 // gfx950 decode kernel with the CN->VN messages in registers: the path of
 // codes with five base rows (the 5 x Nb family), a power-of-two lift Z <= 1024,
-// rows of 19 or 20 edges, 8-bit soft values with E_max > MSG_max and no offset
-// table
+// rows of 19 or 20 edges, 8-bit soft values with E_max > MSG_max, with or without
+// an offset table
 // (arXiv:1903.10107, Secs. 2-3: Eqs. 1, 4, 8, 9, Alg. 1 and Alg. 2).
 //
 // The row-pair arithmetic is the split family's (two lanes per row pair
@@ -45,6 +45,7 @@ struct RegLds {
     uint8_t *syn;     // packed syndrome of the current frame
     uint16_t *addr;   // [threads][MB][DH] E byte address of each lane's slot
     int *flags;       // three vote words, the queue slot, two last-layer test words
+    int *offs;        // offset tables: [offset_iters][MB][DH][2] the slot's offset in both halves
 };
 
 __device__ __forceinline__ RegLds reg_lds(const DecodeArgs &A)
@@ -55,7 +56,24 @@ __device__ __forceinline__ RegLds reg_lds(const DecodeArgs &A)
     M.syn = smem + A.lds_syn_off;
     M.addr = reinterpret_cast<uint16_t *>(smem + A.lds_tab_off);
     M.flags = reinterpret_cast<int *>(smem + A.lds_flag_off);
+    M.offs = reinterpret_cast<int *>(smem + A.lds_flag_off + 32);
     return M;
+}
+
+// The offset table, once per workgroup: for each of its rows, layer b, slot i
+// and lane half h, the offset of the slot's block in both 16-bit halves (both
+// rows of a pair share the block), 0 for padding slots. Read after the
+// stage-in barrier.
+template <int MB, int DH>
+__device__ __forceinline__ void reg_stage_offsets(const DevCode &C, const DecodeArgs &A, const RegLds &M)
+{
+    const int total = C.offset_iters * MB * DH * 2;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        const int slot = q % (MB * DH * 2), row = q / (MB * DH * 2);
+        const int blk = A.lane_tab[slot].w;
+        const unsigned o = (unsigned)(blk >= 0 ? C.offsets[(size_t)row * C.n_blocks + blk] : 0) & 0xffffu;
+        M.offs[q] = (int)(o | o << 16);
+    }
 }
 
 // Per-lane constants of a workgroup: the row pair, the real-slot mask.
@@ -213,11 +231,12 @@ __device__ __forceinline__ int reg_unsat(const RegLds &M, const RegLane &G, unsi
 // b; lk holds the row pair's messages of that layer and receives the new ones.
 // With PAR, also the syndrome test of the row pair on the new soft values: 1 when
 // a row fails. (Used on the last layer, whose variable nodes take their final
-// value of the iteration there.)
-template <int DMIN, int DMAX, int RULE, bool PAR = false>
+// value of the iteration there.) With OFF, the magnitudes lose the offsets of the
+// slots' blocks (orow[2 i] for slot i) and are clamped to [0, MSG_max].
+template <int DMIN, int DMAX, int RULE, bool PAR = false, bool OFF = false>
 __device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, int b, const s16x2 (&e)[DMAX / 2],
                                           const unsigned (&a0)[DMAX / 2], s16x2 (&lk)[DMAX / 2], s16x2 syn,
-                                          unsigned hzb)
+                                          unsigned hzb, const int *orow = nullptr)
 {
     constexpr int DH = DMAX / 2;
     const s16x2 em = splat2(C.e_max);
@@ -253,6 +272,13 @@ __device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, in
     const s16x2 par = xor3(syn, own, swap_pair(own));
     u16x2 out[DH];
     pair_fold<DH, RULE>(p, out);
+    if constexpr (OFF) {
+#pragma unroll
+        for (int i = 0; i < DH; ++i) {
+            const s16x2 oi = __builtin_bit_cast(s16x2, orow[2 * i]);
+            out[i] = as_u(vmin2(vmax2(as_s(out[i]) - oi, splat2(0)), as_s(mm)));
+        }
+    }
     s16x2 ot[DH];
 #pragma unroll
     for (int i = 0; i < DH; ++i) {
@@ -274,8 +300,9 @@ __device__ __forceinline__ int reg_finish(const DevCode &C, const RegLane &G, in
     return 0;
 }
 
-// Decode frame f with one workgroup (address table already built).
-template <int DMIN, int DMAX, int MB, int RULE>
+// Decode frame f with one workgroup (address table, and with OFF the offsets,
+// already staged).
+template <int DMIN, int DMAX, int MB, int RULE, bool OFF>
 __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeArgs &A, const RegLds &M,
                                                  const RegLane &G, int f)
 {
@@ -345,6 +372,10 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
     // clears the word after the next barrier, which every reader has passed.
     for (int t = 1; t <= A.max_iter && !conv; ++t) {
         bool stop = false;
+        // this lane's offsets of iteration t: row min(t - 1, offset_iters - 1)
+        const int *orow_t = nullptr;
+        if constexpr (OFF)
+            orow_t = M.offs + (size_t)(t - 1 < C.offset_iters - 1 ? t - 1 : C.offset_iters - 1) * (MB * DH * 2) + G.h;
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
             // the slot addresses before the barrier that orders the previous
@@ -369,11 +400,12 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
                     break;
                 }
             }
+            const int *orow = OFF ? orow_t + b * DH * 2 : nullptr;
             if (b == MB - 1) {
-                if (reg_finish<DMIN, DMAX, RULE, true>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb))
+                if (reg_finish<DMIN, DMAX, RULE, true, OFF>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb, orow))
                     M.flags[4 + (t & 1)] = 1;
             } else {
-                reg_finish<DMIN, DMAX, RULE>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb);
+                reg_finish<DMIN, DMAX, RULE, false, OFF>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb, orow);
             }
         }
         if (stop)
@@ -442,22 +474,26 @@ __device__ __forceinline__ void reg_decode_frame(const DevCode &C, const DecodeA
 }
 
 // One workgroup per frame (grid = frames).
-template <int DMIN, int DMAX, int MB, int RULE>
+template <int DMIN, int DMAX, int MB, int RULE, bool OFF>
 __global__ __launch_bounds__(1024) void k_decode_frame_reg(DevCode C, DecodeArgs A)
 {
     const RegLds M = reg_lds(A);
+    if constexpr (OFF)
+        reg_stage_offsets<MB, DMAX / 2>(C, A, M);
     const RegLane G = reg_setup<MB, DMAX / 2>(C, A, M);
-    reg_decode_frame<DMIN, DMAX, MB, RULE>(C, A, M, G, blockIdx.x);
+    reg_decode_frame<DMIN, DMAX, MB, RULE, OFF>(C, A, M, G, blockIdx.x);
 }
 
 // Persistent workgroups: each takes the next position of a device queue (reset
 // to 0 by k_queue_reset before the launch), decodes frame order[position] (or
 // position), and stops once the queue is past the last frame, which every wave
 // of every workgroup reaches.
-template <int DMIN, int DMAX, int MB, int RULE>
+template <int DMIN, int DMAX, int MB, int RULE, bool OFF>
 __global__ __launch_bounds__(1024) void k_decode_reg_persistent(DevCode C, DecodeArgs A)
 {
     const RegLds M = reg_lds(A);
+    if constexpr (OFF)
+        reg_stage_offsets<MB, DMAX / 2>(C, A, M);
     const RegLane G = reg_setup<MB, DMAX / 2>(C, A, M);
     for (;;) {
         __syncthreads();  // the previous frame's stage-out is done with E and the queue slot
@@ -469,7 +505,7 @@ __global__ __launch_bounds__(1024) void k_decode_reg_persistent(DevCode C, Decod
             break;
         const int f = A.order ? A.order[q] : q;
         if ((unsigned)f < (unsigned)A.n_frames)
-            reg_decode_frame<DMIN, DMAX, MB, RULE>(C, A, M, G, f);
+            reg_decode_frame<DMIN, DMAX, MB, RULE, OFF>(C, A, M, G, f);
     }
 }
 
@@ -681,10 +717,12 @@ __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs 
             A.out_E[(size_t)f * n + j] = (int16_t)E[j];
 }
 
-template <int DMIN, int DMAX, int MB, int RULE>
+template <int DMIN, int DMAX, int MB, int RULE, bool OFF>
 hipError_t launch_one_reg(const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
 {
     if (A.frames_per_wg > 0) {
+        if (OFF)
+            return hipErrorInvalidValue;  // the several-frames kernel takes no offset table
         const int fw = 64 / C.z, wthreads = 64 * (A.frames_per_wg / fw);
         const size_t wlds = wave_lds_bytes(C.n, C.z, A.syn_bytes, A.frames_per_wg, wthreads, MB, DMAX / 2);
         if (wlds > 65536) {
@@ -698,10 +736,11 @@ hipError_t launch_one_reg(const DevCode &C, const DecodeArgs &A, int threads, si
         return hipGetLastError();
     }
     const bool persistent = A.persistent_wgs > 0;
-    auto kern = persistent ? k_decode_reg_persistent<DMIN, DMAX, MB, RULE> : k_decode_frame_reg<DMIN, DMAX, MB, RULE>;
+    auto kern = persistent ? k_decode_reg_persistent<DMIN, DMAX, MB, RULE, OFF>
+                           : k_decode_frame_reg<DMIN, DMAX, MB, RULE, OFF>;
     if (lds > 65536) {
-        hipError_t e = persistent ? allow_max_lds<k_decode_reg_persistent<DMIN, DMAX, MB, RULE>>()
-                                  : allow_max_lds<k_decode_frame_reg<DMIN, DMAX, MB, RULE>>();
+        hipError_t e = persistent ? allow_max_lds<k_decode_reg_persistent<DMIN, DMAX, MB, RULE, OFF>>()
+                                  : allow_max_lds<k_decode_frame_reg<DMIN, DMAX, MB, RULE, OFF>>();
         if (e != hipSuccess)
             return e;
     }
@@ -717,9 +756,14 @@ hipError_t launch_one_reg(const DevCode &C, const DecodeArgs &A, int threads, si
 template <int DMIN>
 hipError_t launch_rule_reg(int rule, const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
 {
+    if (C.offsets) {
+        if (rule == LDPC_RULE_MINSUM)
+            return launch_one_reg<DMIN, 20, kRegLayers, kRuleMinSum, true>(C, A, threads, lds, s);
+        return launch_one_reg<DMIN, 20, kRegLayers, kRuleRcbpFB, true>(C, A, threads, lds, s);
+    }
     if (rule == LDPC_RULE_MINSUM)
-        return launch_one_reg<DMIN, 20, kRegLayers, kRuleMinSum>(C, A, threads, lds, s);
-    return launch_one_reg<DMIN, 20, kRegLayers, kRuleRcbpFB>(C, A, threads, lds, s);
+        return launch_one_reg<DMIN, 20, kRegLayers, kRuleMinSum, false>(C, A, threads, lds, s);
+    return launch_one_reg<DMIN, 20, kRegLayers, kRuleRcbpFB, false>(C, A, threads, lds, s);
 }
 
 } // namespace
@@ -732,8 +776,7 @@ size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw)
 
 hipError_t launch_decode_reg(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)
 {
-    if (C.mb != kRegLayers || P.split_dmax != 20 || P.min_deg < 19 || P.acc_bits != 8 || C.offsets ||
-        C.e_max <= C.msg_max)
+    if (C.mb != kRegLayers || P.split_dmax != 20 || P.min_deg < 19 || P.acc_bits != 8 || C.e_max <= C.msg_max)
         return hipErrorInvalidValue;
     return launch_rule_reg<19>(P.cn_rule, C, A, P.threads, P.lds_bytes, s);
 }

@@ -49,7 +49,7 @@ struct LaunchPlan {
     int split_dmax;   // split kernel (two lanes per row pair) with this slot count, or 0
     bool split_global_l; // split kernel with L in a global slice per workgroup (E stays in LDS)
     bool layer_sync;  // one launch per layer over all frames, E and L in global slices per frame
-    bool split_reg;   // split arithmetic with L in registers (five base rows, 8-bit E, no offsets)
+    bool split_reg;   // split arithmetic with L in registers (five base rows, 8-bit E)
     size_t lds_bytes; // dynamic LDS per workgroup
 };
 

@@ -76,15 +76,7 @@ def test_offset_tables_on_every_family(B, name, family):
     except B.LdpcError as e:
         assert e.code == B.LDPC_EUNSUPPORTED
         pytest.skip(f"{family} does not apply to {name}: {e}")
-    if family == "split_reg":
-        # the register-resident family takes no offset table; automatic
-        # selection then falls back to the split family
-        with pytest.raises(B.LdpcError) as ei:
-            B.Code(code.base, z, kernel=family, cn_rule=2, offsets=off)
-        assert ei.value.code == B.LDPC_EUNSUPPORTED
-        assert B.Code(code.base, z, cn_rule=2, offsets=off).plan()["kernel"] == "split"
-        return
-    gc = B.Code(code.base, z, kernel=family, cn_rule=2, offsets=off)   # offsets narrow no other family
+    gc = B.Code(code.base, z, kernel=family, cn_rule=2, offsets=off)   # offsets narrow no family
     assert gc.plan()["kernel"] == family
     _say(f"[gpu family offsets] {name} {family} {gc.plan()}")
     got = B.decode(gc, fr.syn, fr.llr, 40, want_state=True)

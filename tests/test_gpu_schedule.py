@@ -62,13 +62,15 @@ def test_persistent_schedule_matches_oracle(B, wgs, ordered):
     assert np.array_equal(iters.cpu().numpy(), ref["iters"])
 
 
-def test_persistent_schedule_with_offset_table(B):
+@pytest.mark.parametrize("family", ["split_reg", "split"])
+def test_persistent_schedule_with_offset_table(B, family):
     import torch
     code = I.Code(I.make_base(5, 32, 256), 256)
     fr = I.make_frames(code, 24, 0.02, 8, n_short=int(0.2 * code.n))
     off = np.random.default_rng(3).integers(-2, 6, size=(5, code.n_blocks)).astype(np.int8)
-    gc = B.Code(code.base, code.z, cn_rule=B.LDPC_RULE_MINSUM, offsets=off)
-    assert gc.plan()["kernel"] == "split"
+    kw = {} if family == "split_reg" else {"kernel": family}   # automatic selection picks split_reg
+    gc = B.Code(code.base, code.z, cn_rule=B.LDPC_RULE_MINSUM, offsets=off, **kw)
+    assert gc.plan()["kernel"] == family
     _say(f"[gpu schedule] persistent with offsets {gc.plan()}")
     F = fr.n_frames
     bits, conv, iters = _outs(code, F)
