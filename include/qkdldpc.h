@@ -69,7 +69,7 @@ typedef struct {
                                row min(t-1, offset_iters-1), result clamped to [0, msg_max];
                                copied at create. NULL = no offsets (the paper's decoder).
                                Every kernel family serves them (LDPC_KERNEL_SPLIT_REG while
-                               its LDS holds the table; not with frames_per_workgroup). */
+                               its LDS holds the table). */
     int32_t offset_iters;   /* rows of offsets; must be >= 1 when offsets != NULL */
     int32_t kernel_hint;    /* 0: pick the kernel family automatically; LDPC_HINT_*: use that
                                family, or fail with LDPC_EUNSUPPORTED when it does not apply
@@ -208,8 +208,7 @@ typedef struct {
     int32_t frames_per_workgroup;  /* 0: one frame per workgroup. > 0: that many frames per
                                       workgroup, each frame's z lanes inside one wave (64 / z
                                       frames per wave, no workgroup barrier); needs the
-                                      LDPC_KERNEL_SPLIT_REG family with z <= 64 and no offset
-                                      table, a multiple of
+                                      LDPC_KERNEL_SPLIT_REG family with z <= 64, a multiple of
                                       64 / z, at most 16 waves per workgroup, all frames' soft
                                       values within 64 KB of LDS, and no persistent schedule
                                       (LDPC_EUNSUPPORTED / LDPC_EINVAL otherwise). */

@@ -305,9 +305,9 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
             return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup < 0");
         if (fpw > 0) {
             const int z = code->h.z;
-            if (!code->plan.split_reg || z > 64 || !code->h.offsets.empty())
-                return fail(LDPC_EUNSUPPORTED, "ldpc_schedule: frames_per_workgroup needs the split_reg family "
-                                               "with z <= 64 and no offset table");
+            if (!code->plan.split_reg || z > 64)
+                return fail(LDPC_EUNSUPPORTED,
+                            "ldpc_schedule: frames_per_workgroup needs the split_reg family with z <= 64");
             const int fw = 64 / z;
             if (fpw % fw != 0 || fpw / fw > 16)
                 return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup must be a multiple of 64 / z, "
@@ -318,7 +318,8 @@ int check_decode_args(const ldpc_code *code, const uint8_t *syndromes, const int
             const size_t esz = ((size_t)code->h.n + z + 15) & ~(size_t)15;
             if ((size_t)fpw * esz > 65536)
                 return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup frames' soft values exceed 64 KB");
-            const size_t lds = qkdldpc::wave_reg_lds_bytes(code->h.n, z, (code->h.m + 7) / 8, fpw);
+            const size_t lds = qkdldpc::wave_reg_lds_bytes(code->h.n, z, (code->h.m + 7) / 8, fpw,
+                                                           code->h.offsets.empty() ? 0 : code->h.offset_iters);
             if (lds > (size_t)code->lds_limit)
                 return fail(LDPC_EINVAL, "ldpc_schedule: frames_per_workgroup needs more LDS than a workgroup has");
         }

@@ -522,12 +522,14 @@ __global__ __launch_bounds__(1024) void k_decode_reg_persistent(DevCode C, Decod
 // ---------------------------------------------------------------------------
 
 // LDS of the wave kernel: frame slot k's E (plus dummy column) at k * esz, its
-// syndrome at syn_off + k * syn_bytes, then the per-lane address table.
+// syndrome at syn_off + k * syn_bytes, then the per-lane address table and,
+// with an offset table, its rows as in the one-frame kernels.
 struct WaveGeom {
     int fpw;        // frames per workgroup
     int esz;        // bytes per frame slot's E region (n + Z rounded up to 16)
     int syn_off;    // LDS offset of the syndromes
     int tab_off;    // LDS offset of the address table
+    int off_off;    // LDS offset of the staged offsets
 };
 
 __host__ __device__ inline WaveGeom wave_geom(int n, int z, int syn_bytes, int fpw, int threads, int mb, int dh)
@@ -537,19 +539,18 @@ __host__ __device__ inline WaveGeom wave_geom(int n, int z, int syn_bytes, int f
     g.esz = (n + z + 15) & ~15;
     g.syn_off = fpw * g.esz;
     g.tab_off = (g.syn_off + fpw * syn_bytes + 15) & ~15;
-    (void)threads;
-    (void)mb;
-    (void)dh;
+    g.off_off = (g.tab_off + threads * mb * dh * 2 + 15) & ~15;
     return g;
 }
 
-__host__ __device__ inline size_t wave_lds_bytes(int n, int z, int syn_bytes, int fpw, int threads, int mb, int dh)
+__host__ __device__ inline size_t wave_lds_bytes(int n, int z, int syn_bytes, int fpw, int threads, int mb, int dh,
+                                                 int offset_iters)
 {
     const WaveGeom g = wave_geom(n, z, syn_bytes, fpw, threads, mb, dh);
-    return (size_t)g.tab_off + (size_t)threads * mb * dh * 2;
+    return (size_t)g.off_off + (size_t)offset_iters * mb * dh * 2 * 4;
 }
 
-template <int DMIN, int DMAX, int MB, int RULE>
+template <int DMIN, int DMAX, int MB, int RULE, bool OFF>
 __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs A)
 {
     constexpr int DH = DMAX / 2;
@@ -573,6 +574,13 @@ __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs 
     M.syn = syn_s;
     M.addr = reinterpret_cast<uint16_t *>(smem + W.tab_off);
     M.flags = nullptr;
+    M.offs = reinterpret_cast<int *>(smem + W.off_off);
+    if constexpr (OFF) {
+        // the offsets every frame of the workgroup uses: the kernel's one
+        // workgroup barrier, before any wave's control flow depends on its frames
+        reg_stage_offsets<MB, DH>(C, A, M);
+        __syncthreads();
+    }
     RegLane G;
     G.tid = tid;
     G.nthr = blockDim.x;
@@ -636,6 +644,10 @@ __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs 
     for (int t = 1; t <= A.max_iter; ++t) {
         if (__ballot(!done) == 0)
             break;
+        // this lane's offsets of iteration t: row min(t - 1, offset_iters - 1)
+        const int *orow_t = nullptr;
+        if constexpr (OFF)
+            orow_t = M.offs + (size_t)(t - 1 < C.offset_iters - 1 ? t - 1 : C.offset_iters - 1) * (MB * DH * 2) + G.h;
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
             unsigned a0[DH];
@@ -659,7 +671,8 @@ __global__ __launch_bounds__(1024) void k_decode_wave_reg(DevCode C, DecodeArgs 
                 }
             }
             if (!done)
-                reg_finish<DMIN, DMAX, RULE>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb);
+                reg_finish<DMIN, DMAX, RULE, false, OFF>(C, G, b, e, a0, Lr[b], reg_syn(synm, b), hzb,
+                                                         OFF ? orow_t + b * DH * 2 : nullptr);
             // the next layer's reads come after these writes in program order
             __builtin_amdgcn_wave_barrier();
         }
@@ -721,17 +734,16 @@ template <int DMIN, int DMAX, int MB, int RULE, bool OFF>
 hipError_t launch_one_reg(const DevCode &C, const DecodeArgs &A, int threads, size_t lds, hipStream_t s)
 {
     if (A.frames_per_wg > 0) {
-        if (OFF)
-            return hipErrorInvalidValue;  // the several-frames kernel takes no offset table
         const int fw = 64 / C.z, wthreads = 64 * (A.frames_per_wg / fw);
-        const size_t wlds = wave_lds_bytes(C.n, C.z, A.syn_bytes, A.frames_per_wg, wthreads, MB, DMAX / 2);
+        const size_t wlds = wave_lds_bytes(C.n, C.z, A.syn_bytes, A.frames_per_wg, wthreads, MB, DMAX / 2,
+                                           OFF ? C.offset_iters : 0);
         if (wlds > 65536) {
-            hipError_t e = allow_max_lds<k_decode_wave_reg<DMIN, DMAX, MB, RULE>>();
+            hipError_t e = allow_max_lds<k_decode_wave_reg<DMIN, DMAX, MB, RULE, OFF>>();
             if (e != hipSuccess)
                 return e;
         }
         const int grid = (A.n_frames + A.frames_per_wg - 1) / A.frames_per_wg;
-        auto wkern = k_decode_wave_reg<DMIN, DMAX, MB, RULE>;
+        auto wkern = k_decode_wave_reg<DMIN, DMAX, MB, RULE, OFF>;
         hipLaunchKernelGGL(wkern, dim3(grid), dim3(wthreads), wlds, s, C, A);
         return hipGetLastError();
     }
@@ -768,10 +780,10 @@ hipError_t launch_rule_reg(int rule, const DevCode &C, const DecodeArgs &A, int 
 
 } // namespace
 
-size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw)
+size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw, int offset_iters)
 {
     const int fw = 64 / z;
-    return wave_lds_bytes(n, z, syn_bytes, fpw, 64 * (fpw / fw), kRegLayers, 10);
+    return wave_lds_bytes(n, z, syn_bytes, fpw, 64 * (fpw / fw), kRegLayers, 10, offset_iters);
 }
 
 hipError_t launch_decode_reg(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s)

@@ -62,7 +62,7 @@ hipError_t launch_decode_pairs(const LaunchPlan &P, const DevCode &C, const Deco
 hipError_t launch_decode_split(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 hipError_t launch_decode_reg(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 // LDS bytes of the split_reg decode with fpw frames per workgroup (Z <= 64)
-size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw);
+size_t wave_reg_lds_bytes(int n, int z, int syn_bytes, int fpw, int offset_iters);
 hipError_t launch_decode_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, hipStream_t s);
 // The layer-synchronous decode in three phases, for callers that stop early:
 // stage-in and the iteration-0 check; iterations t0..t1; stage-out.

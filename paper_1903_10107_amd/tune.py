@@ -104,10 +104,8 @@ class Runner:
         self.code = B.Code(base, z, acc_bits=acc_bits, kernel=sched.kernel, **code_kw)
         if sched.persistent_workgroups and self.code.plan()["kernel"] not in B.PERSISTENT_FAMILIES:
             raise B.LdpcError(B.LDPC_EUNSUPPORTED, "persistent schedule needs the split family")
-        if sched.frames_per_workgroup and (self.code.plan()["kernel"] != "split_reg" or z > 64 or
-                                           code_kw.get("offsets") is not None):
-            raise B.LdpcError(B.LDPC_EUNSUPPORTED,
-                              "frames per workgroup need split_reg with Z <= 64 and no offset table")
+        if sched.frames_per_workgroup and (self.code.plan()["kernel"] != "split_reg" or z > 64):
+            raise B.LdpcError(B.LDPC_EUNSUPPORTED, "frames per workgroup need split_reg with Z <= 64")
         F = llr.shape[0]
         self.F = F
         self.syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()

@@ -1,8 +1,9 @@
 """Offset tables on the register-resident family (split_reg): the magnitudes of
 the check-node messages lose a per-iteration, per-base-edge offset and are
 clamped to [0, MSG_max] (the offset form of the check node, with the offsets the
-learned decoder quantizes), on the one-frame-per-workgroup and the persistent
-kernels, for both check-node rules; compared with the oracle bit for bit."""
+learned decoder quantizes), on the one-frame-per-workgroup, the persistent and
+the several-frames-per-workgroup kernels, for both check-node rules; compared
+with the oracle bit for bit."""
 import sys
 
 import numpy as np
@@ -56,17 +57,28 @@ def test_split_reg_offsets_match_oracle(B, name, rule):
         assert np.array_equal(got[k], ref[k]), (name, rule, k)
 
 
-def test_frames_per_workgroup_refuses_offset_tables(B):
+@pytest.mark.parametrize("rule", ["rcbp", "minsum"])
+@pytest.mark.parametrize("fpw", [2, 8])
+def test_frames_per_workgroup_with_offsets_matches_oracle(B, fpw, rule):
+    """The several-frames-per-workgroup kernel (Z = 32: two frames per wave) with
+    an offset table: the staged offsets are shared by the workgroup's frames."""
     import torch
-    code = I.Code(I.make_base(5, 32, 32), 32)
-    off = np.zeros((2, code.n_blocks), dtype=np.int8)
-    gc = B.Code(code.base, 32, cn_rule=B.LDPC_RULE_MINSUM, offsets=off)
+    z, F, T = 32, 20, 40
+    code = I.Code(I.make_base(5, 32, z), z)
+    fr = I.make_frames(code, F, 0.01, 91 + fpw, n_short=0)
+    off = np.random.default_rng(fpw).integers(-1, 3, size=(3, code.n_blocks)).astype(np.int8)
+    cn = B.LDPC_RULE_RCBP_FB if rule == "rcbp" else B.LDPC_RULE_MINSUM
+    gc = B.Code(code.base, z, cn_rule=cn, offsets=off)
     assert gc.plan()["kernel"] == "split_reg"
-    fr = I.make_frames(code, 4, 0.02, 9)
-    bits = torch.zeros((4, code.n // 8), dtype=torch.uint8, device="cuda")
-    conv = torch.zeros(4, dtype=torch.uint8, device="cuda")
-    iters = torch.zeros(4, dtype=torch.int32, device="cuda")
-    with pytest.raises(B.LdpcError) as ei:
-        B.ldpc_decode_batch_sched(gc, torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda(), 4, 10,
-                                  bits, conv, iters, frames_per_workgroup=2)
-    assert ei.value.code == B.LDPC_EUNSUPPORTED
+    _say(f"[gpu split_reg offsets] fpw={fpw} {rule}")
+    bits = torch.zeros((F, code.n // 8), dtype=torch.uint8, device="cuda")
+    conv = torch.zeros(F, dtype=torch.uint8, device="cuda")
+    iters = torch.zeros(F, dtype=torch.int32, device="cuda")
+    B.ldpc_decode_batch_sched(gc, torch.from_numpy(fr.syn).cuda(), torch.from_numpy(fr.llr).cuda(), F, T,
+                              bits, conv, iters, frames_per_workgroup=fpw)
+    torch.cuda.synchronize()
+    ref = O.decode(code.base, z, fr.syn, fr.llr, T,
+                   cn_rule=O.RULE_RCBP_FB if rule == "rcbp" else O.RULE_MINSUM, offsets=off)
+    assert np.array_equal(bits.cpu().numpy(), ref["bits"])
+    assert np.array_equal(conv.cpu().numpy(), ref["conv"])
+    assert np.array_equal(iters.cpu().numpy(), ref["iters"])
