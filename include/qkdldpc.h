@@ -207,9 +207,10 @@ typedef struct {
                                       has finished; results are the same. */
     int32_t frames_per_workgroup;  /* 0: one frame per workgroup. > 0: that many frames per
                                       workgroup, each frame's z lanes inside one wave (64 / z
-                                      frames per wave, no workgroup barrier); needs the
-                                      LDPC_KERNEL_SPLIT_REG family with z <= 64, a multiple of
-                                      64 / z, at most 16 waves per workgroup, all frames' soft
+                                      frames per wave, no workgroup barrier in the decode);
+                                      needs the LDPC_KERNEL_SPLIT_REG family with z <= 64, a
+                                      multiple of 64 / z, at most 16 waves per workgroup, all
+                                      frames' soft
                                       values within 64 KB of LDS, and no persistent schedule
                                       (LDPC_EUNSUPPORTED / LDPC_EINVAL otherwise). */
 } ldpc_schedule;

@@ -513,7 +513,8 @@ __global__ __launch_bounds__(1024) void k_decode_reg_persistent(DevCode C, Decod
 // Several frames per workgroup for lifts of at most 64 (frames_per_workgroup in
 // the schedule): a frame's Z lanes (two per row pair) lie in one wave, so a wave
 // decodes 64 / Z frames on its own and a workgroup of W waves decodes
-// W x 64 / Z frames with no workgroup barrier at all. Within a wave the LDS
+// W x 64 / Z frames with no workgroup barrier in the decode (one at the start,
+// after an offset table is staged, is the only one). Within a wave the LDS
 // instructions execute in program order, so a layer's E reads follow the
 // previous layer's E writes without a barrier; the syndrome tests are wave
 // ballots over each frame's lanes. Frames of one wave run in lockstep: a frame
