@@ -210,9 +210,9 @@ typedef struct {
                                       frames per wave, no workgroup barrier in the decode);
                                       needs the LDPC_KERNEL_SPLIT_REG family with z <= 64, a
                                       multiple of 64 / z, at most 16 waves per workgroup, all
-                                      frames' soft
-                                      values within 64 KB of LDS, and no persistent schedule
-                                      (LDPC_EUNSUPPORTED / LDPC_EINVAL otherwise). */
+                                      frames' soft values within 64 KB of LDS, and no
+                                      persistent schedule (LDPC_EUNSUPPORTED / LDPC_EINVAL
+                                      otherwise). */
 } ldpc_schedule;
 
 /* ldpc_decode_batch_ex with a schedule (NULL = default): frames are independent
