@@ -1121,6 +1121,11 @@ def main():
                                      args.pipelined_streams)
     if args.batched_frames:
         out["batched"] = batched(wl, code, n_short, args.batched_frames, args.steps, args.warmup)
+        if "least_shortening" in pts:
+            # the batched form at the least shortening with FER <= 1e-2: it does not
+            # wait for one batch's slowest frame, so this is where it pays most
+            pts["least_shortening"]["batched"] = batched(wl, code, args.least_short, args.batched_frames,
+                                                         args.steps, args.warmup)
     if args.ragged_frames:
         out["ragged"] = ragged(args.ragged_frames, args.steps, args.warmup)
     if args.learned_steps:
