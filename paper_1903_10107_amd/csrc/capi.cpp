@@ -176,8 +176,8 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
             c->lds_tab_off = (int)(e_sp + l_len + round_up(syn_bytes, 16));
             c->lds_flag_off = (int)(c->lds_tab_off + tab);
             c->ws_l_off = 0;
-            // L of all layers: one chunk of ceil(dh / 2) dwords per lane, row pair and layer
-            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * h.z * 4 * ((dh + 1) / 2), 256) : 0;
+            // L of all layers: a chunk of 4 dh bytes per row pair and layer
+            c->ws_frame_bytes = glob_l ? round_up((size_t)h.mb * (h.z / 2) * 4 * dh, 256) : 0;
             c->lane_tab_bytes = tab;
             return true;
         }
@@ -195,7 +195,7 @@ bool make_plan(ldpc_code *c, int lds_limit, int hint)
         P.lds_bytes = 0;
         P.threads = (int)std::min<size_t>(1024, 2 * round_up((size_t)h.z / 2, 32));
         c->ws_l_off = round_up(((size_t)h.n + h.z) * esize, 256);
-        c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.mb * h.z * 4 * ((dh + 1) / 2), 256);
+        c->ws_frame_bytes = c->ws_l_off + round_up((size_t)h.mb * (h.z / 2) * 4 * dh, 256);
         c->lane_tab_bytes = (size_t)h.mb * dh * 2 * 16;
         return true;
     }

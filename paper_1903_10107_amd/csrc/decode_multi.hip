@@ -14,7 +14,7 @@
 // pair, both rows in the 16-bit halves, Alg. 1 in forward-backward order, Eq. 9
 // under Alg. 2); E lives in a global slice per frame and is read and written at
 // the QC-shifted positions, L in the global-L chunk layout
-// [layer][row pair][lane][ceil(DH/2) dwords]. Iteration 1 takes L = 0 unread.
+// [layer][row pair][4 DH bytes]. Iteration 1 takes L = 0 unread.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -199,8 +199,8 @@ __global__ __launch_bounds__(1024) void k_multi_layer(DevCode C, DecodeArgs A, i
         return;
     const unsigned zm = (unsigned)(z - 1);
     ET *E = frame_e<ET>(A, f);
-    const LRef<DH, true> Lr{reinterpret_cast<uint32_t *>(frame_l(A, f) +
-                                                         (((size_t)b * hz + r) * 2 + h) * LRef<DH, true>::BYTES)};
+    const LRef<DH, true> Lr{frame_l(A, f) + (size_t)b * hz * LRef<DH, true>::PAIR_BYTES,
+                            (unsigned)r * LRef<DH, true>::PAIR_BYTES, h};
     SplitRow<DH> R;
     const int32_t *off_row = nullptr;
     if constexpr (OFF)  // row min(t - 1, offset_iters - 1) of the offset table
@@ -252,7 +252,8 @@ __global__ __launch_bounds__(256) void k_multi_stage_out(DevCode C, DecodeArgs A
             const int b = v / (4 * DH), rem = v - b * 4 * DH;
             A.out_L[(size_t)f * ne + e] =
                 none ? (int8_t)0
-                     : (int8_t)Lg[(((size_t)b * hz + r) * 2 + (rem & 1)) * LRef<DH, true>::BYTES + (rem & ~1) + half];
+                     : (int8_t)Lg[((size_t)b * hz + r) * LRef<DH, true>::PAIR_BYTES +
+                                  LRef<DH, true>::slot_byte(rem & 1, rem >> 1) + half];
         }
     }
 }

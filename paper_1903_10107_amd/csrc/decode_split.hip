@@ -26,9 +26,9 @@ namespace qkdldpc {
 // added per access. L of a row pair is laid out [layer][half][slot][lane].
 //
 // L lives in LDS when it fits beside E; otherwise (LG) it streams from a
-// global workspace slice per workgroup laid out [layer][row pair][lane][slot
-// byte pairs], so each lane moves its 2 x DH bytes with dword accesses and a
-// wave touches one contiguous run. The first iteration takes L = 0 without
+// global workspace slice per workgroup laid out [layer][row pair][4 DH bytes]
+// (a 16-bit slot per byte pair, the two lanes' slots side by side, see LRef),
+// so a wave touches one contiguous run and no byte goes unused. The first iteration takes L = 0 without
 // reading it, so the slice needs no clearing between frames.
 //
 // When every row pair has a lane pair (Z/2 <= RPL x threads/2, with RPL row
@@ -86,8 +86,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
     const LdsESink<ET> es{hzb};
     auto lref = [&](int b, int r) {
         if constexpr (LG)
-            return LRef<DH, true>{
-                reinterpret_cast<uint32_t *>(Lg + (((size_t)b * hz + r) * 2 + h) * LRef<DH, true>::BYTES)};
+            return LRef<DH, true>{Lg + (size_t)b * hz * LRef<DH, true>::PAIR_BYTES,
+                                  (unsigned)r * LRef<DH, true>::PAIR_BYTES, h};
         else
             return LRef<DH, false>{L + r * S + h + b * 4 * DH};
     };
@@ -230,22 +230,18 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             // keep the slice base uniform, so the loads fill the slot registers
             // in place.
             int rr[RPL];
+            unsigned ro[RPL];  // chunk offsets of the lane's row pairs within a layer
 #pragma unroll
-            for (int k = 0; k < RPL; ++k)
+            for (int k = 0; k < RPL; ++k) {
                 rr[k] = lp + k * np;
-            auto chunk = [&](int b, int k) {
-                return reinterpret_cast<uint32_t *>(
-                    Lg + (unsigned)(((b * hz + rr[k]) * 2 + h) * LRef<DH, true>::BYTES));
-            };
+                ro[k] = (unsigned)rr[k] * LRef<DH, true>::PAIR_BYTES;
+            }
+            auto layer_l = [&](int b) { return Lg + (size_t)b * hz * LRef<DH, true>::PAIR_BYTES; };
             uint32_t pf[PD][RPL][NW] = {};
             auto fetch = [&](uint32_t (&dst)[RPL][NW], int b) {
 #pragma unroll
-                for (int k = 0; k < RPL; ++k) {
-                    const uint32_t *c = chunk(b, k);
-#pragma unroll
-                    for (int q = 0; q < NW; ++q)
-                        dst[k][q] = c[q];
-                }
+                for (int k = 0; k < RPL; ++k)
+                    LRef<DH, true>::fetch(layer_l(b), ro[k], h, dst[k]);
             };
             int t = 1, b = 0;
             bool done = conv || A.max_iter == 0;
@@ -265,14 +261,11 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) {
                         split_fetch_e<ET>(R[k], hzb);
+                        s16x2 lw[DH];
+                        LRef<DH, true>::unpack(pf[j][k], h, lw);
 #pragma unroll
-                        for (int q = 0; q < NW; ++q) {
-                            s16x2 lo, hi;
-                            LRef<DH, true>::unpack(pf[j][k][q], lo, hi);
-                            R[k].lk[2 * q] = t >= 2 ? lo : zero;
-                            if (2 * q + 1 < DH)
-                                R[k].lk[2 * q + 1] = t >= 2 ? hi : zero;
-                        }
+                        for (int i = 0; i < DH; ++i)
+                            R[k].lk[i] = t >= 2 ? lw[i] : zero;
                     }
                     if (b == 0 && t >= 2) {
                         int fail0 = 0;
@@ -294,7 +287,7 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
                     fetch(pf[j], b + PD >= C.mb ? b + PD - C.mb : b + PD);
 #pragma unroll
                     for (int k = 0; k < RPL; ++k)
-                        split_finish<DMIN, DMAX, ET, RULE, true, OFF>(C, R[k], LRef<DH, true>{chunk(b, k)},
+                        split_finish<DMIN, DMAX, ET, RULE, true, OFF>(C, R[k], LRef<DH, true>{layer_l(b), ro[k], h},
                                                                       syn_of(k, b), es);
                     if (++b == C.mb) {
                         b = 0;
@@ -367,8 +360,8 @@ __device__ __forceinline__ void split_decode_frame(const DevCode &C, const Decod
             if constexpr (LG) {
                 const int b = v / (4 * DH), rem = v - b * 4 * DH;
                 x = iters == 0 ? (int8_t)0
-                               : (int8_t)Lg[(((size_t)b * hz + r) * 2 + (rem & 1)) * LRef<DH, true>::BYTES +
-                                            (rem & ~1) + half];
+                               : (int8_t)Lg[((size_t)b * hz + r) * LRef<DH, true>::PAIR_BYTES +
+                                            LRef<DH, true>::slot_byte(rem & 1, rem >> 1) + half];
             } else {
                 x = L[r * S + v + half * 2 * DH];
             }

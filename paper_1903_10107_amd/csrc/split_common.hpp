@@ -108,14 +108,64 @@ struct LRef<DH, false> {
     }
 };
 
-// Global: ceil(DH/2) dwords (the chunk of one lane); dword k holds slot 2k
-// (lower half, upper half) in bytes 0 and 1 and slot 2k+1 in bytes 2 and 3
-// (zero past the last slot). zero: take L = 0 unread.
+// Global: the chunk of one row pair and layer is 4 DH bytes, a 16-bit slot
+// (lower half, upper half) per byte pair, nothing unused. Slots 2k and 2k+1 of a
+// lane share a dword. DH even: lane 0's DH/2 dwords, then lane 1's. DH odd: lane
+// 0's (DH-1)/2 dwords, one dword holding the last slot of lane 0 (low half) and
+// of lane 1 (high half), then lane 1's dwords; each lane then reads its
+// (DH+1)/2 dwords in one aligned load (lane 1's start at the shared dword) and
+// writes its dwords and its 16-bit half of the shared one. Addresses are a base
+// uniform over the workgroup plus a 32-bit per-lane offset. zero: take L = 0
+// unread.
 template <int DH>
 struct LRef<DH, true> {
-    static constexpr int NW = (DH + 1) / 2;
-    static constexpr int BYTES = 4 * NW;
-    uint32_t *p;
+    static constexpr int NW = (DH + 1) / 2;  // dwords one lane reads
+    static constexpr int ND = DH / 2;        // dwords one lane writes whole
+    static constexpr bool ODD = DH & 1;
+    static constexpr int PAIR_BYTES = 4 * DH;
+    uint8_t *base;
+    unsigned off;  // byte offset of the row pair's chunk
+    int h;         // lane of the pair
+    static __host__ __device__ __forceinline__ unsigned read_off(int h) { return (unsigned)h * 4u * ND; }
+    static __host__ __device__ __forceinline__ unsigned dword_off(int h) { return (unsigned)h * 4u * NW; }
+    static __host__ __device__ __forceinline__ unsigned short_off(int h) { return 4u * ND + 2u * (unsigned)h; }
+    // byte of slot s's lower half in the chunk (for a readback of L)
+    static __host__ __device__ __forceinline__ unsigned slot_byte(int h, int s)
+    {
+        return ODD && s == DH - 1 ? short_off(h) : dword_off(h) + 2u * (unsigned)s;
+    }
+    static __device__ __forceinline__ void fetch(const uint8_t *base, unsigned off, int h, uint32_t (&w)[NW])
+    {
+        const uint32_t *d = reinterpret_cast<const uint32_t *>(base + (off + read_off(h)));
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            w[k] = d[k];
+    }
+    // slot registers from the words fetch() read: bytes (x, x+1) of the word
+    // pair move to the top of the two 16-bit halves, then an arithmetic shift.
+    // DH odd: lane 1's slot words start one dword later, and the last slots
+    // sit in the shared dword (lane 0: word ND, bytes 0-1; lane 1: word 0,
+    // bytes 2-3).
+    static __device__ __forceinline__ void unpack(const uint32_t (&w)[NW], int h, s16x2 (&lk)[DH])
+    {
+        if constexpr (ODD) {
+            const unsigned sl = h ? 0x050c040cu : 0x010c000cu, sh = h ? 0x070c060cu : 0x030c020cu;
+            const unsigned st = h ? 0x030c020cu : 0x050c040cu;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                lk[2 * k] = cell(__builtin_amdgcn_perm(w[k + 1], w[k], sl));
+                lk[2 * k + 1] = cell(__builtin_amdgcn_perm(w[k + 1], w[k], sh));
+            }
+            lk[DH - 1] = cell(__builtin_amdgcn_perm(w[ND], w[0], st));
+        } else {
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                lk[2 * k] = cell(__builtin_amdgcn_perm(w[k], w[k], 0x010c000cu));
+                lk[2 * k + 1] = cell(__builtin_amdgcn_perm(w[k], w[k], 0x030c020cu));
+            }
+        }
+    }
+    static __device__ __forceinline__ s16x2 cell(unsigned x) { return __builtin_bit_cast(s16x2, x) >> (short)8; }
     __device__ __forceinline__ void load(s16x2 (&lk)[DH], bool zero) const
     {
         if (zero) {
@@ -124,30 +174,23 @@ struct LRef<DH, true> {
                 lk[i] = splat2(0);
             return;
         }
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            s16x2 lo, hi;
-            unpack(p[k], lo, hi);
-            lk[2 * k] = lo;
-            if (2 * k + 1 < DH)
-                lk[2 * k + 1] = hi;
-        }
+        uint32_t w[NW];
+        fetch(base, off, h, w);
+        unpack(w, h, lk);
     }
-    // bytes (b0, b1, b2, b3) -> slots (b0, b1) and (b2, b3): each byte moves to
-    // the top of a 16-bit half, then an arithmetic shift per half
-    static __device__ __forceinline__ void unpack(uint32_t w, s16x2 &lo, s16x2 &hi)
+    // low bytes of the two 16-bit halves of a and of b, in that order
+    static __device__ __forceinline__ uint32_t pack(s16x2 a, s16x2 b)
     {
-        lo = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x010c000cu)) >> (short)8;
-        hi = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(w, w, 0x030c020cu)) >> (short)8;
+        return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, b), __builtin_bit_cast(uint32_t, a), 0x06040200u);
     }
     __device__ __forceinline__ void store(const s16x2 (&ln)[DH]) const
     {
+        uint32_t *d = reinterpret_cast<uint32_t *>(base + (off + dword_off(h)));
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const uint32_t a = __builtin_bit_cast(uint32_t, ln[2 * k]);
-            const uint32_t b = 2 * k + 1 < DH ? __builtin_bit_cast(uint32_t, ln[2 * k + 1]) : 0u;
-            p[k] = (a & 0xffu) | ((a >> 8) & 0xff00u) | ((b & 0xffu) << 16) | ((b << 8) & 0xff000000u);
-        }
+        for (int k = 0; k < ND; ++k)
+            d[k] = pack(ln[2 * k], ln[2 * k + 1]);
+        if constexpr (ODD)
+            *reinterpret_cast<uint16_t *>(base + (off + short_off(h))) = (uint16_t)pack(ln[DH - 1], ln[DH - 1]);
     }
 };
 
