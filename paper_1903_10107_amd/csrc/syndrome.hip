@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "syndrome_words.hpp"
@@ -86,6 +87,95 @@ __global__ __launch_bounds__(256) void k_syndrome_words(DevCode C, const uint32_
     }
 }
 
+// kSynFpw frames per workgroup, their packed bits staged in LDS with every
+// column block written twice in a row (2 Z/32 words), so that the two words an
+// entry funnel-shifts, (k + s/32) and (k + s/32 + 1), never wrap: an entry costs
+// one add, one paired LDS read, one alignbit and one XOR. x is read from memory
+// once, in 16-byte loads when the frames are 16-byte aligned and Z/32 is a
+// multiple of 4, every load of a thread issued before its stores. Threads map
+// to (frame, block row, word) pairs with no per-word division.
+// Dynamic LDS: int2 {doubled-block word index + s/32, s mod 32} per nonzero
+// block, int2 {first block, degree} per base row, then (16-byte aligned at
+// x_off) the frames.
+constexpr int kSynFpw = 4;
+
+// i / d for 0 <= i < 2^22 and d >= 1, from rd = 1/d in float: the product is
+// within 1 of i / d there, and one step each way corrects it
+__device__ __forceinline__ int div_small(int i, int d, float rd)
+{
+    int q = (int)((float)i * rd);
+    q -= q * d > i;
+    q += (q + 1) * d <= i;
+    return q;
+}
+
+__global__ __launch_bounds__(256) void k_syndrome_words_lds(DevCode C, const uint32_t *__restrict__ bits, int n_frames,
+                                                           int x_off, uint32_t *__restrict__ out_syn)
+{
+    extern __shared__ __align__(16) int2 s_tab[];
+    int2 *s_rows = s_tab + C.n_blocks;
+    uint32_t *s_x = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(s_tab) + x_off);
+    const int wz = C.z >> 5, xw = C.n >> 5, sw = C.m >> 5, mb = C.mb;
+    const int f0 = blockIdx.x * kSynFpw, tid = threadIdx.x, nthr = blockDim.x;
+    const int nf = n_frames - f0 < kSynFpw ? n_frames - f0 : kSynFpw;
+    const uint32_t *x = bits + (size_t)f0 * xw;
+    for (int e = tid; e < C.n_blocks; e += nthr) {
+        const int sh = C.shift[e];
+        s_tab[e] = make_int2(2 * (C.colbase[e] >> 5) + (sh >> 5), sh & 31);
+    }
+    for (int r = tid; r < mb; r += nthr)
+        s_rows[r] = make_int2(C.blk_off[r], C.deg[r]);
+    // frame word i = c wz + k goes to 2 c wz + k and 2 c wz + wz + k; loads and
+    // stores are unconditional (an index past the end takes the last word,
+    // which is then stored again with its own value), so no load waits behind
+    // a branch
+    constexpr int U = 4;
+    auto stage = [&](const auto *src, auto *dst, int total, int bw) {  // bw: block width in elements
+        const float rbw = 1.0f / (float)bw;
+        std::remove_const_t<std::remove_pointer_t<decltype(src)>> v[U];
+        for (int i0 = tid; i0 < total; i0 += U * nthr) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = src[i0 + u * nthr < total ? i0 + u * nthr : total - 1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * nthr < total ? i0 + u * nthr : total - 1;
+                const int c = div_small(i, bw, rbw), d = i + c * bw;  // 2 c bw + (i - c bw)
+                dst[d] = v[u];
+                dst[d + bw] = v[u];
+            }
+        }
+    };
+    if (((uintptr_t)x & 15) == 0 && (wz & 3) == 0)
+        stage(reinterpret_cast<const uint4 *>(x), reinterpret_cast<uint4 *>(s_x), nf * (xw >> 2), wz >> 2);
+    else
+        stage(x, s_x, nf * xw, wz);
+    __syncthreads();
+    // kl lanes take the words of one (frame, block row) pair, the workgroup
+    // slots / pairs at a time
+    const int kl = wz < nthr ? wz : nthr, slots = nthr / kl;
+    const int slot = tid / kl, k0 = tid - slot * kl;
+    if (slot >= slots)
+        return;
+    int j = slot / mb, b = slot - j * mb;  // pair p = j mb + b, advanced by slots
+    for (int p = slot; p < nf * mb; p += slots) {
+        const int2 r = s_rows[b];
+        const uint32_t *xj = s_x + (size_t)j * 2 * xw;
+        for (int k = k0; k < wz; k += kl) {
+            uint32_t acc = 0;
+#pragma unroll 4
+            for (int e = r.x; e < r.x + r.y; ++e) {
+                const int2 t = s_tab[e];
+                const uint32_t *q = xj + t.x + k;
+                acc ^= __builtin_amdgcn_alignbit(q[1], q[0], (uint32_t)t.y);
+            }
+            out_syn[(size_t)(f0 + j) * sw + b * wz + k] = acc;
+        }
+        for (b += slots; b >= mb; b -= mb)
+            ++j;
+    }
+}
+
 // The same words with the frames grouped by XCD: the hardware hands workgroup
 // p to XCD p mod 8, so workgroup p takes frame (p mod 8) + 8 j, where j counts
 // that XCD's frames, and the j-th frame's words are split over bpf workgroups.
@@ -145,6 +235,20 @@ hipError_t launch_syndrome(const DevCode &C, const uint8_t *bits, int n_frames, 
                 }
                 hipLaunchKernelGGL(k_syndrome_words_xcd, dim3((unsigned)xcd_blocks), dim3(256), tab_bytes, s, C, xw,
                                    n_frames, (int)bpf, sw);
+                return hipGetLastError();
+            }
+            // a workgroup per frame with the frame in LDS, where the batch fills
+            // the chip and a frame has at least a wave of syndrome words
+            const size_t x_off = (tab_bytes + 15) & ~(size_t)15;
+            const size_t lds_bytes = x_off + (size_t)kSynFpw * (C.n >> 5) * 8;  // every block twice
+            if (n_frames >= 256 * kSynFpw && words >= 64 && lds_bytes <= (size_t)lds_limit) {
+                if (lds_bytes > 65536) {
+                    hipError_t e = allow_max_lds<k_syndrome_words_lds>();
+                    if (e != hipSuccess)
+                        return e;
+                }
+                hipLaunchKernelGGL(k_syndrome_words_lds, dim3((unsigned)((n_frames + kSynFpw - 1) / kSynFpw)),
+                                   dim3(256), lds_bytes, s, C, xw, n_frames, (int)x_off, sw);
                 return hipGetLastError();
             }
             const long long blocks = (total + 255) / 256;
