@@ -187,9 +187,10 @@ def test_binding_rejects_short_buffers(B):
     (5, 32, 32, 5, 0),       # word kernel (Z a multiple of 32, fewer than 8 frames), one partial workgroup
     (4, 12, 37, 5, 0),       # Z not a multiple of 32: bit kernel
     (5, 32, 1024, 5, 0),     # word kernel, the n = 32768 code
-    (5, 32, 1024, 300, 0),   # many frames: a workgroup per frame, the frame staged in LDS (16-byte loads)
-    (5, 32, 1024, 260, 4),   # the same with buffers 4- but not 16-byte aligned (dword loads)
-    (5, 32, 256, 300, 0),    # Z = 256: 40 syndrome words per frame, the grid-stride word kernel
+    (5, 32, 1024, 300, 0),   # word kernel, many frames (workgroups span frames)
+    (5, 32, 1024, 1030, 0),  # >= 1024 frames: four frames per workgroup staged in LDS (16-byte loads), last one 2
+    (5, 32, 1024, 1027, 4),  # the same with buffers 4- but not 16-byte aligned (dword loads), last workgroup 3
+    (5, 32, 256, 1100, 0),   # Z = 256: 40 syndrome words per frame, too few for the LDS kernel
     (10, 64, 16384, 11, 0),  # word kernel grouped by XCD (the n = 2^20 code), frames not a multiple of 8
     (4, 32, 16384, 8, 0),    # grouped by XCD, exactly 8 workgroups per frame
     (3, 8, 96, 130, 0),      # Z = 3 x 32, not a power of two: 3 words per block
