@@ -124,7 +124,11 @@ int ldpc_code_dims(const ldpc_code *code, int32_t *n, int32_t *m, int64_t *n_edg
  * out_bits:  DEVICE uint8 [n_frames][ceil(n/8)], hard decisions [E_j < 0], packed.
  * out_converged: DEVICE uint8 [n_frames], 1 iff H x^ = s.
  * n_frames = 0 is a no-op. May allocate a stream-ordered workspace for codes
- * whose state does not fit on chip (see ldpc_workspace_bytes). */
+ * whose state does not fit on chip (see ldpc_workspace_bytes). Returns
+ * LDPC_EINVAL for a NULL code or buffer, n_frames < 0, max_iter < 0, more than
+ * 65535 frames on the layer-synchronous family, or a code created on another
+ * device than the current one; LDPC_EDEVICE when the workspace allocation or a
+ * launch fails. */
 int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
                       int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
                       uint8_t *out_converged, void *stream);
@@ -138,8 +142,10 @@ int ldpc_decode_batch(const ldpc_code *code, const uint8_t *syndromes, const int
  *            in row-major base order, row r of the block at index r.
  * out_E:     DEVICE int16 [n_frames][n]: final soft values.
  * workspace: DEVICE buffer of at least ldpc_workspace_bytes(code, n_frames)
- *            bytes (may be NULL when that size is 0); no allocation happens
- *            when it is given. */
+ *            bytes, or NULL (the call then allocates it stream-ordered when
+ *            that size is not 0); no allocation happens when it is given, and
+ *            a smaller workspace_bytes is LDPC_EINVAL.
+ * Other errors as for ldpc_decode_batch. */
 int ldpc_decode_batch_ex(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
                          int32_t n_frames, int32_t max_iter, uint8_t *out_bits,
                          uint8_t *out_converged, int32_t *out_iters, int8_t *out_L,
@@ -284,9 +290,18 @@ void ldpc_batch_destroy(ldpc_batch *batch);
 int ldpc_order_by_unsat(const ldpc_code *code, const uint8_t *syndromes, const int8_t *llr_in,
                         int32_t n_frames, int32_t *out_unsat, int32_t *out_order, void *stream);
 
-/* Alice's side of the syndrome exchange: out_syn = H bits for a batch.
- * bits: DEVICE uint8 [n_frames][ceil(n/8)] packed; out_syn: DEVICE uint8
- * [n_frames][ceil(m/8)] packed. */
+/* Alice's side of the syndrome exchange (Sec. 2: she sends s = H x over the
+ * public channel): out_syn = H bits over GF(2) for a batch, with the code's QC
+ * structure (check row b Z + r reads bit c Z + ((r + shift) mod Z) of every
+ * nonzero block (b, c)).
+ *   bits     DEVICE uint8 [n_frames][ceil(n/8)], bit j -> byte j>>3, bit (j&7)
+ *   out_syn  DEVICE uint8 [n_frames][ceil(m/8)], the same packing (the syndromes
+ *            ldpc_decode_batch takes)
+ * The caller owns both buffers; any alignment is accepted (4-byte aligned
+ * buffers take the word-parallel kernels). Uses no workspace and allocates
+ * nothing; asynchronous on stream. Returns LDPC_EINVAL for a NULL code or
+ * buffer, n_frames < 0 (0 is a no-op) or a code created on another device than
+ * the current one, LDPC_EDEVICE when a launch fails. */
 int ldpc_syndrome_batch(const ldpc_code *code, const uint8_t *bits, int32_t n_frames,
                         uint8_t *out_syn, void *stream);
 
