@@ -187,14 +187,20 @@ __global__ __launch_bounds__(1024) void k_multi_layer(DevCode C, DecodeArgs A, i
 {
     constexpr int DH = DMAX / 2;
     __shared__ int4 s_tab[2 * DH];
-    const int f = blockIdx.y;
-    if (!frame_flags(A, f)[0])
-        return;
     const int tid = threadIdx.x, h = tid & 1, z = C.z, hz = z >> 1;
+    // One workgroup per chunk of np row pairs of a frame, on a 1-D grid padded to
+    // a multiple of 8. Workgroup p runs on XCD p mod 8, and XCD k takes the k-th
+    // eighth of the (frame, chunk) pairs in order: neighbouring chunks of a frame,
+    // whose QC-shifted E windows share their boundary lines, then meet in one L2.
+    const int np = blockDim.x >> 1, ch = (hz + np - 1) / np;
+    const int q = (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    const int f = q / ch, chunk = q - f * ch;
+    if (f >= A.n_frames || !frame_flags(A, f)[0])
+        return;  // uniform over the workgroup
     if (tid < 2 * DH)
         s_tab[tid] = A.lane_tab[b * DH * 2 + tid];
     __syncthreads();
-    const int r = blockIdx.x * (blockDim.x >> 1) + (tid >> 1);
+    const int r = chunk * np + (tid >> 1);
     if (r >= hz)
         return;
     const unsigned zm = (unsigned)(z - 1);
@@ -262,6 +268,8 @@ namespace {
 
 // Launch phases: stage-in and the iteration-0 check and retirement (0),
 // iterations t0..t1 (1), stage-out (2).
+constexpr int kLayerThreads = 512;
+
 template <int DMIN, int DMAX, typename ET, int RULE, bool OFF>
 hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A, int phase, int t0, int t1,
                      hipStream_t s)
@@ -269,6 +277,12 @@ hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A,
     const int F = A.n_frames, hz = C.z / 2;
     const int np = P.threads / 2;
     const dim3 rows((hz + np - 1) / np, F);
+    // layer launches in smaller workgroups than the check: at the layer
+    // kernel's register count a CU then holds several, and one's loads overlap
+    // another's arithmetic
+    const int lt = P.threads < kLayerThreads ? P.threads : kLayerThreads;
+    const unsigned lch = (unsigned)((hz + lt / 2 - 1) / (lt / 2));
+    const dim3 layer_grid(8 * (((unsigned)F * lch + 7) / 8));
     const dim3 elems((C.n + 1023) / 1024 < 64 ? (C.n + 1023) / 1024 : 64, F);
     const dim3 fin((F + 255) / 256);
     if (phase == 0) {
@@ -284,7 +298,7 @@ hipError_t run_multi(const LaunchPlan &P, const DevCode &C, const DecodeArgs &A,
     hipError_t e = hipSuccess;
     for (int t = t0; t <= t1 && e == hipSuccess; ++t) {
         for (int b = 0; b < C.mb; ++b)
-            hipLaunchKernelGGL((k_multi_layer<DMIN, DMAX, ET, RULE, OFF>), rows, dim3(P.threads), 0, s, C, A, b, t);
+            hipLaunchKernelGGL((k_multi_layer<DMIN, DMAX, ET, RULE, OFF>), layer_grid, dim3(lt), 0, s, C, A, b, t);
         hipLaunchKernelGGL((k_multi_check<DMIN, DMAX, ET>), rows, dim3(P.threads), 0, s, C, A);
         hipLaunchKernelGGL(k_multi_finalize, fin, dim3(256), 0, s, A, t);
         e = hipGetLastError();
